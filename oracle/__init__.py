@@ -1,0 +1,22 @@
+"""FP64 CPU oracle for the ALE Galerkin-Boltzmann nodal DG method.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously-correct
+reimplementation of the method, written from the paper (arXiv 2607.00199,
+"A High-Order ALE DG Method for the Boltzmann Equation in Nearly Incompressible
+Flows"), that the GPU library is checked against.  Only the test-suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it.  It shares
+no code with the GPU library (``paper_2607_00199_amd``) and neither imports the
+other; both only read the seeded synthetic inputs in ``workloads``.
+
+Everything is numpy float64.  Each module cites the passage of the paper it
+follows.  Where the paper is silent, garbled or ambiguous the oracle takes the
+reading listed in the design notes (flux sign convention, SARK row-sum typo,
+cubature degree, 3D moment system); functions whose result is not pinned to
+anything the paper or mathematics fixes say "parity unpinned" in their
+docstring.
+
+Parity-unpinned parts (see the individual docstrings):
+  * the 3D 10-field moment system (the paper only cites it);
+  * the wall / far-field ghost states and the sponge layer used as a stand-in
+    for the paper's perfectly matched layer (the paper only names the PML).
+"""
