@@ -1,0 +1,216 @@
+/*
+ * gb.h -- C ABI of the MI355X library for the ALE nodal DG Galerkin-Boltzmann
+ * hot path (arXiv 2607.00199, "A High-Order ALE DG Method for the Boltzmann
+ * Equation in Nearly Incompressible Flows").
+ *
+ * What the library computes
+ *   The semi-discrete ALE form of the Galerkin-Boltzmann moment system
+ *   (Section 2, eq. ale_bns; Section 3, eq. semi_discrete_form) on a moving
+ *   mesh of straight-sided simplices (triangles: 6 fields, tetrahedra: 10
+ *   fields), advanced by the four-stage semi-analytic Runge-Kutta method
+ *   (Section 4) with the geometric factors rebuilt from the vertex positions
+ *   at every stage (Section 5).  Every step of that path runs in HIP kernels
+ *   on one gfx950 GPU.
+ *
+ * Conventions shared by all calls
+ *   - Every call returns gb_status; GB_OK is 0.  On any other status,
+ *     gb_last_error() returns a thread-local message.  No C++ exception
+ *     crosses this interface.
+ *   - Host arrays are plain C arrays owned by the caller; the library copies
+ *     what it needs and never keeps a host pointer.
+ *   - Field layout of every state array is [K][NF][Np] (element, field,
+ *     node), FP64 on the host.  Field order: rho, m_x, m_y, S_xy, S_xx/sqrt2,
+ *     S_yy/sqrt2 in 2D (the q1..q6 of Section 2, with rho u = c m_x); in 3D
+ *     rho, m_x, m_y, m_z, S_xy, S_xz, S_yz, S_xx/sqrt2, S_yy/sqrt2, S_zz/sqrt2.
+ *   - Node order inside an element is the lattice order of the Warp & Blend
+ *     nodes (Section 3): s-rows outer, r inner (3D: t, s, r).
+ *   - Faces: triangle (v0,v1), (v1,v2), (v2,v0); tetrahedron (v0,v1,v2),
+ *     (v0,v1,v3), (v1,v2,v3), (v0,v2,v3).
+ *   - Handles are single-threaded: one context drives one HIP stream.
+ *   - Kernel faults inside the hot path (an element with J <= 0, a
+ *     non-positive density or a NaN) are latched on the device and reported
+ *     as GB_ERR_MESH / GB_ERR_NONPHYSICAL by the next synchronising call.
+ */
+#ifndef GB_H
+#define GB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GB_OK = 0,
+    GB_ERR_ARG = 1,          /* invalid argument (null pointer, size, range)      */
+    GB_ERR_MESH = 2,         /* J <= 0, unmatched face, inconsistent period       */
+    GB_ERR_OOM = 3,          /* device allocation failed                          */
+    GB_ERR_DEVICE = 4,       /* HIP runtime error                                 */
+    GB_ERR_NONPHYSICAL = 5,  /* latched on the device: density <= 0 or NaN        */
+    GB_ERR_STATE = 6,        /* call out of order (e.g. stepping without a state) */
+    GB_ERR_UNSUPPORTED = 7   /* (dim, N, precision) combination not built         */
+} gb_status;
+
+typedef enum { GB_FP64 = 0, GB_FP32 = 1 } gb_precision;
+
+/* Upwinding of the surface flux (Section 3, eq. upwind_flux).
+ * SPLIT: the stationary part A.n and the ALE part w.n are upwinded
+ *        separately, as the paper writes it.
+ * RELATIVE: the characteristic speeds c*lambda_k - w.n are upwinded together. */
+typedef enum { GB_FLUX_SPLIT = 0, GB_FLUX_RELATIVE = 1 } gb_flux_mode;
+
+/* Face tags for gb_mesh_create (face_tag may be NULL: every unmatched face is
+ * then an error).  Interior and periodic faces are found automatically. */
+enum { GB_FACE_INTERIOR = 0, GB_FACE_WALL = 1, GB_FACE_FARFIELD = 2 };
+
+/* Prescribed mesh motions (Section 5: the grid velocity is given at the
+ * vertices and interpolated linearly; vertices move with classical RK4).
+ * Displacement d(X, t) of a vertex with reference position X, x = X + d:
+ *   NONE
+ *   SIN_PRODUCT_2D  eq. gcl_exact_field:
+ *     d = (p[0], p[1]) sin(2 pi t/p[2]) sin(2 pi (X-p[5])/p[3]) sin(2 pi (Y-p[6])/p[4])
+ *   TRIPLE_PRODUCT_3D  eq. TGV_deformation, amplitude p[0], period p[1], box p[2]:
+ *     d_x = p[0] sin(2 pi t/p[1]) sin(2 pi (Y+p[2]/2)/p[2]) sin(2 pi (Z+p[2]/2)/p[2]), cyclic
+ *   PLUNGE_BLEND_2D  the plunge y = Y - h0 sin(omega t) of Section 7.3 times a
+ *     radial weight B(r) = 1 for r <= p[2], cosine ramp to 0 at r = p[3],
+ *     r = |X - (p[4], p[5])|; h0 = p[0], omega = p[1].  (The weight is this
+ *     library's addition so the outer boundary stays fixed.) */
+typedef enum {
+    GB_MOTION_NONE = 0,
+    GB_MOTION_SIN_PRODUCT_2D = 1,
+    GB_MOTION_TRIPLE_PRODUCT_3D = 2,
+    GB_MOTION_PLUNGE_BLEND_2D = 3
+} gb_motion_kind;
+
+typedef struct {
+    int kind;          /* gb_motion_kind */
+    double p[8];       /* parameters, meaning per kind above */
+} gb_motion;
+
+/* Solver parameters.  c = sqrt(RT); tau is the relaxation time (nu = tau c^2,
+ * Section 2).  rho0 is the density offset of FP32 storage: the FP32 path
+ * stores q1 - rho0 so O(Ma^2) density fluctuations keep their digits; it is
+ * ignored for FP64.  cubature_degree: exactness degree of the collapsed
+ * Gauss-Jacobi rule for the relaxation term (0 = 3N; must be >= 2N).
+ * q_inf: far-field / sponge state (NF values, FP64).  The sponge adds
+ * -sigma(r) (q - q_inf), sigma = sigma_max ((r - r0)/(r1 - r0))^2 for
+ * r0 < r (r measured from (cx, cy)); sigma_max = 0 disables it.  Wall, far
+ * field and sponge are stand-ins for the paper's wall treatment and perfectly
+ * matched layer, which it names without giving their form. */
+typedef struct {
+    double c;
+    double tau;
+    int precision;         /* gb_precision */
+    int flux_mode;         /* gb_flux_mode */
+    double rho0;
+    int cubature_degree;
+    double q_inf[10];
+    double sponge_cx, sponge_cy, sponge_r0, sponge_r1, sponge_sigma_max;
+} gb_params;
+
+typedef struct gb_ctx gb_ctx;
+typedef struct gb_mesh gb_mesh;
+typedef struct gb_solver gb_solver;
+
+/* Last error message of this thread (never NULL). */
+const char *gb_last_error(void);
+
+/* Library version string. */
+const char *gb_version(void);
+
+/* Create a context on HIP device `device` that enqueues all work on the HIP
+ * stream `stream` (a hipStream_t, or NULL for the default stream). */
+gb_status gb_ctx_create(int device, void *stream, gb_ctx **out);
+void gb_ctx_destroy(gb_ctx *ctx);
+/* Block until all work the context enqueued has finished. */
+gb_status gb_ctx_synchronize(gb_ctx *ctx);
+
+/* Build a mesh (Section 3: K non-overlapping, straight-sided, positively
+ * oriented simplices with a fixed topology).
+ *   dim      2 or 3;  N  polynomial order (2D: 1..5, 3D: 1..3)
+ *   vx       [nv][dim] reference (t = 0) vertex coordinates
+ *   etov     [K][dim+1] vertex indices, every element with J > 0
+ *   period   [dim] box period per direction, 0 = not periodic; NULL = none.
+ *            Periodic images are matched modulo the period; vertices on
+ *            opposite sides stay separate vertices.
+ *   face_tag [K][dim+1] GB_FACE_* for faces without a partner; NULL = none.
+ * Builds the reference operators, the element connectivity and the
+ * node-to-node trace map (vmapP) on the host and uploads them once.
+ * Errors: GB_ERR_ARG, GB_ERR_MESH (J <= 0, unmatched untagged face),
+ * GB_ERR_UNSUPPORTED, GB_ERR_OOM. */
+gb_status gb_mesh_create(gb_ctx *ctx, int dim, int N, int64_t nv, const double *vx,
+                         int64_t K, const int32_t *etov, const double *period,
+                         const int8_t *face_tag, gb_mesh **out);
+void gb_mesh_destroy(gb_mesh *mesh);
+
+/* Sizes: Np nodes per element, NF fields, Nfaces*Nfp face nodes per
+ * element, Nc cubature points (for the given degree, 0 = 3N). */
+gb_status gb_mesh_sizes(const gb_mesh *mesh, int64_t *K, int *Np, int *NF, int *Nfp, int *Nfaces);
+
+/* Reference-operator export (host computation, no GPU work), for checking
+ * the host setup: which = 0..2 differentiation matrix D_r, D_s, D_t [Np][Np];
+ * 3 LIFT [Np][Nfaces*Nfp] (faces parametrised with reference measure 2);
+ * 4 cubature interpolation [Nc][Np]; 5 projection [Np][Nc]; 6 nodes [Np][dim];
+ * 7 mass matrix [Np][Np].  `out` must hold the stated size; `n_out` receives
+ * the element count written. */
+gb_status gb_ref_operator(int dim, int N, int cubature_degree, int which, double *out,
+                          int64_t capacity, int64_t *n_out);
+
+/* Current node coordinates [K][dim][Np] (host output). */
+gb_status gb_mesh_nodes(const gb_mesh *mesh, double *xyz);
+
+/* Current vertex coordinates [nv][dim] (host output). */
+gb_status gb_mesh_vertices(const gb_mesh *mesh, double *vx);
+
+/* Set the prescribed motion (Section 5).  May be called before or between
+ * steps; the current vertex positions are kept. */
+gb_status gb_set_motion(gb_mesh *mesh, const gb_motion *motion);
+
+/* Create a solver on a mesh.  Allocates the four resident state arrays of the
+ * SARK-4 schedule in device memory.  The solver keeps a reference to the
+ * mesh: destroy the solver first. */
+gb_status gb_solver_create(gb_mesh *mesh, const gb_params *params, gb_solver **out);
+void gb_solver_destroy(gb_solver *solver);
+
+/* Device bytes gb_solver_create would allocate for this mesh and params
+ * (state arrays only; the mesh's own tables are counted by the mesh). */
+gb_status gb_solver_footprint(const gb_mesh *mesh, const gb_params *params, size_t *bytes);
+
+/* Set the state q [K][NF][Np] (FP64 host) and the time t0. */
+gb_status gb_state_set(gb_solver *solver, const double *q, double t0);
+
+/* Copy the state to the host (FP64 [K][NF][Np]); also returns the time and
+ * the number of steps taken.  Synchronises and reports latched errors. */
+gb_status gb_state_get(gb_solver *solver, double *q, double *t, int64_t *step);
+
+/* F = L(q) + P Ntilde(I q) for q [K][NF][Np] (FP64 host in and out) at the
+ * current vertex positions, with the grid velocity at the current time: the
+ * right-hand side of eq. time_split without the stiff -Lambda q part
+ * (Section 4).  Does not change the solver state.  Synchronises. */
+gb_status gb_rhs(gb_solver *solver, const double *q, double *F);
+
+/* Advance nsteps SARK-4 steps of size dt (Section 4) on the context's
+ * stream.  Asynchronous: returns after enqueueing.  The vertex positions
+ * move with the prescribed motion by classical RK4 (Section 5). */
+gb_status gb_sark_step(gb_solver *solver, double dt, int64_t nsteps);
+
+/* Same as gb_sark_step, replaying a captured HIP graph of one step; the
+ * graph is rebuilt when dt changes. */
+gb_status gb_sark_step_graph(gb_solver *solver, double dt, int64_t nsteps);
+
+/* Stage-kernel timing.  gb_solver_time_stages(solver, 1) resets the counters
+ * and brackets every later stage launch of gb_sark_step with a HIP event pair
+ * on the context's stream (graph replays are not timed).  gb_solver_stage_time
+ * synchronises on the last event and returns the average launch duration in
+ * milliseconds and the number of launches measured since the reset. */
+gb_status gb_solver_time_stages(gb_solver *solver, int enable);
+gb_status gb_solver_stage_time(gb_solver *solver, double *avg_ms, int64_t *launches);
+/* Per stage kind (0..3) average launch duration in ms, same measurement. */
+gb_status gb_solver_stage_time_by_kind(gb_solver *solver, double *avg_ms4);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GB_H */

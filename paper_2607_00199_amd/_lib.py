@@ -1,0 +1,253 @@
+"""ctypes binding of the C ABI in include/gb.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libgb.so`` next to this file.  The
+binding converts numpy arrays to plain pointers and raises ``GbError`` on any
+status other than GB_OK.  It fails loudly when the library is missing: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgb.so")
+
+GB_OK, GB_ERR_ARG, GB_ERR_MESH, GB_ERR_OOM, GB_ERR_DEVICE, GB_ERR_NONPHYSICAL, GB_ERR_STATE, GB_ERR_UNSUPPORTED = range(8)
+GB_FP64, GB_FP32 = 0, 1
+GB_FLUX_SPLIT, GB_FLUX_RELATIVE = 0, 1
+GB_FACE_INTERIOR, GB_FACE_WALL, GB_FACE_FARFIELD = 0, 1, 2
+GB_MOTION_NONE, GB_MOTION_SIN_PRODUCT_2D, GB_MOTION_TRIPLE_PRODUCT_3D, GB_MOTION_PLUNGE_BLEND_2D = range(4)
+
+STATUS_NAMES = {0: "GB_OK", 1: "GB_ERR_ARG", 2: "GB_ERR_MESH", 3: "GB_ERR_OOM", 4: "GB_ERR_DEVICE",
+                5: "GB_ERR_NONPHYSICAL", 6: "GB_ERR_STATE", 7: "GB_ERR_UNSUPPORTED"}
+
+
+class GbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class gb_motion(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_double * 8)]
+
+
+class gb_params(C.Structure):
+    _fields_ = [("c", C.c_double), ("tau", C.c_double), ("precision", C.c_int), ("flux_mode", C.c_int),
+                ("rho0", C.c_double), ("cubature_degree", C.c_int), ("q_inf", C.c_double * 10),
+                ("sponge_cx", C.c_double), ("sponge_cy", C.c_double), ("sponge_r0", C.c_double),
+                ("sponge_r1", C.c_double), ("sponge_sigma_max", C.c_double)]
+
+
+_P = C.c_void_p
+_i64 = C.c_int64
+_dp = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "gb_last_error": (C.c_char_p, []),
+    "gb_version": (C.c_char_p, []),
+    "gb_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+    "gb_ctx_destroy": (None, [_P]),
+    "gb_ctx_synchronize": (C.c_int, [_P]),
+    "gb_mesh_create": (C.c_int, [_P, C.c_int, C.c_int, _i64, _dp, _i64, C.POINTER(C.c_int32), _dp,
+                                 C.POINTER(C.c_int8), C.POINTER(_P)]),
+    "gb_mesh_destroy": (None, [_P]),
+    "gb_mesh_sizes": (C.c_int, [_P, C.POINTER(_i64), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "gb_ref_operator": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _i64, C.POINTER(_i64)]),
+    "gb_mesh_nodes": (C.c_int, [_P, _dp]),
+    "gb_mesh_vertices": (C.c_int, [_P, _dp]),
+    "gb_set_motion": (C.c_int, [_P, C.POINTER(gb_motion)]),
+    "gb_solver_create": (C.c_int, [_P, C.POINTER(gb_params), C.POINTER(_P)]),
+    "gb_solver_destroy": (None, [_P]),
+    "gb_solver_footprint": (C.c_int, [_P, C.POINTER(gb_params), C.POINTER(C.c_size_t)]),
+    "gb_state_set": (C.c_int, [_P, _dp, C.c_double]),
+    "gb_state_get": (C.c_int, [_P, _dp, _dp, C.POINTER(_i64)]),
+    "gb_rhs": (C.c_int, [_P, _dp, _dp]),
+    "gb_sark_step": (C.c_int, [_P, C.c_double, _i64]),
+    "gb_sark_step_graph": (C.c_int, [_P, C.c_double, _i64]),
+    "gb_solver_time_stages": (C.c_int, [_P, C.c_int]),
+    "gb_solver_stage_time": (C.c_int, [_P, _dp, C.POINTER(_i64)]),
+    "gb_solver_stage_time_by_kind": (C.c_int, [_P, _dp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libgb.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                              "(run __graft_entry__.build() or python -m paper_2607_00199_amd.build)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != GB_OK:
+        raise GbError(status, load().gb_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- same-named calls
+
+def gb_version() -> str:
+    return load().gb_version().decode()
+
+
+def gb_ctx_create(device: int = 0, stream: int = 0):
+    out = _P()
+    _check(load().gb_ctx_create(device, _P(stream or None), C.byref(out)))
+    return out
+
+
+def gb_ctx_destroy(ctx):
+    load().gb_ctx_destroy(ctx)
+
+
+def gb_ctx_synchronize(ctx):
+    _check(load().gb_ctx_synchronize(ctx))
+
+
+def gb_mesh_create(ctx, dim: int, N: int, vx, etov, period=None, face_tag=None):
+    vx = _f64(vx)
+    etov = np.ascontiguousarray(etov, dtype=np.int32)
+    per = None if period is None else _f64(period)
+    tag = None if face_tag is None else np.ascontiguousarray(face_tag, dtype=np.int8)
+    out = _P()
+    _check(load().gb_mesh_create(ctx, dim, N, vx.shape[0], _dptr(vx), etov.shape[0],
+                                 etov.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 None if per is None else _dptr(per),
+                                 None if tag is None else tag.ctypes.data_as(C.POINTER(C.c_int8)),
+                                 C.byref(out)))
+    return out
+
+
+def gb_mesh_destroy(mesh):
+    load().gb_mesh_destroy(mesh)
+
+
+def gb_mesh_sizes(mesh):
+    K, Np, NF, Nfp, Nf = _i64(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    _check(load().gb_mesh_sizes(mesh, C.byref(K), C.byref(Np), C.byref(NF), C.byref(Nfp), C.byref(Nf)))
+    return K.value, Np.value, NF.value, Nfp.value, Nf.value
+
+
+def gb_ref_operator(dim: int, N: int, which: int, cubature_degree: int = 0, capacity: int = 1 << 20):
+    buf = np.zeros(capacity)
+    n = _i64()
+    _check(load().gb_ref_operator(dim, N, cubature_degree, which, _dptr(buf), capacity, C.byref(n)))
+    return buf[:n.value].copy()
+
+
+def gb_mesh_nodes(mesh, dim: int) -> np.ndarray:
+    K, Np, *_ = gb_mesh_sizes(mesh)
+    out = np.zeros((K, dim, Np))
+    _check(load().gb_mesh_nodes(mesh, _dptr(out)))
+    return out
+
+
+def gb_mesh_vertices(mesh, nv: int, dim: int) -> np.ndarray:
+    out = np.zeros((nv, dim))
+    _check(load().gb_mesh_vertices(mesh, _dptr(out)))
+    return out
+
+
+def gb_set_motion(mesh, kind: int, params=()):
+    m = gb_motion()
+    m.kind = kind
+    for i, v in enumerate(params):
+        m.p[i] = float(v)
+    _check(load().gb_set_motion(mesh, C.byref(m)))
+
+
+def make_params(c: float, tau: float, precision: int = GB_FP64, flux_mode: int = GB_FLUX_SPLIT,
+                rho0: float = 1.0, cubature_degree: int = 0, q_inf=None, sponge=None) -> gb_params:
+    p = gb_params()
+    p.c, p.tau, p.precision, p.flux_mode = c, tau, precision, flux_mode
+    p.rho0, p.cubature_degree = rho0, cubature_degree
+    if q_inf is not None:
+        for i, v in enumerate(q_inf):
+            p.q_inf[i] = float(v)
+    if sponge is not None:
+        p.sponge_cx, p.sponge_cy, p.sponge_r0, p.sponge_r1, p.sponge_sigma_max = map(float, sponge)
+    return p
+
+
+def gb_solver_create(mesh, params: gb_params):
+    out = _P()
+    _check(load().gb_solver_create(mesh, C.byref(params), C.byref(out)))
+    return out
+
+
+def gb_solver_destroy(solver):
+    load().gb_solver_destroy(solver)
+
+
+def gb_solver_footprint(mesh, params: gb_params) -> int:
+    n = C.c_size_t()
+    _check(load().gb_solver_footprint(mesh, C.byref(params), C.byref(n)))
+    return n.value
+
+
+def gb_state_set(solver, q, t0: float = 0.0):
+    q = _f64(q)
+    _check(load().gb_state_set(solver, _dptr(q), t0))
+
+
+def gb_state_get(solver, shape):
+    q = np.zeros(shape)
+    t = C.c_double()
+    step = _i64()
+    _check(load().gb_state_get(solver, _dptr(q), C.byref(t), C.byref(step)))
+    return q, t.value, step.value
+
+
+def gb_rhs(solver, q) -> np.ndarray:
+    q = _f64(q)
+    F = np.zeros_like(q)
+    _check(load().gb_rhs(solver, _dptr(q), _dptr(F)))
+    return F
+
+
+def gb_sark_step(solver, dt: float, nsteps: int):
+    _check(load().gb_sark_step(solver, dt, nsteps))
+
+
+def gb_sark_step_graph(solver, dt: float, nsteps: int):
+    _check(load().gb_sark_step_graph(solver, dt, nsteps))
+
+
+def gb_solver_time_stages(solver, enable: bool):
+    _check(load().gb_solver_time_stages(solver, 1 if enable else 0))
+
+
+def gb_solver_stage_time(solver):
+    ms = C.c_double()
+    n = _i64()
+    _check(load().gb_solver_stage_time(solver, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def gb_solver_stage_time_by_kind(solver):
+    out = np.zeros(4)
+    _check(load().gb_solver_stage_time_by_kind(solver, _dptr(out)))
+    return out

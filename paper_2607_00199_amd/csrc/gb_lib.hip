@@ -1,0 +1,811 @@
+// C ABI of the ALE Galerkin-Boltzmann library: handles, host setup, device
+// buffers and kernel launches.  See include/gb.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gb.h"
+#include "gb_stage.hpp"
+#include "host_ref.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+gb_status fail(gb_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define GB_HIP(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail(GB_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t n) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = n;
+        return n ? hipMalloc(&p, n) : hipSuccess;
+    }
+    template <typename U>
+    U *as() const { return static_cast<U *>(p); }
+};
+
+}  // namespace
+
+struct gb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    size_t max_lds = 65536;
+};
+
+struct gb_mesh {
+    gb_ctx *ctx = nullptr;
+    int dim = 2, N = 1;
+    int64_t K = 0, nv = 0;
+    gbh::RefElement ref;            // with the default cubature degree
+    gbh::Connectivity conn;
+    std::vector<double> X;          // reference vertex positions (host)
+    DevBuf d_etov, d_X, d_x, d_vmapP;
+    gbd::Motion motion{};
+    int64_t motion_serial = 0;      // bumped by every gb_set_motion
+    int solvers = 0;
+};
+
+struct gb_solver {
+    gb_mesh *mesh = nullptr;
+    gb_params prm{};
+    gbh::RefElement ref;            // with the solver's cubature degree
+    int NF = 6;
+    size_t elem_bytes = 4;
+    DevBuf Q, A, B, G;              // the four resident arrays
+    DevBuf ops, fmask, clock, err;
+    DevBuf vstage, wstage;          // per-stage vertex positions [5][nv][dim] and velocities [4][nv][dim]
+    DevBuf kconst;                  // gbd::KConst<T> for the current dt
+    std::vector<unsigned char> kconst_host;
+    double kconst_dt = -1.0;
+    int64_t kconst_motion_serial = -1;
+    double t = 0.0;
+    int64_t step = 0;
+    bool has_state = false;
+    int epb = 1;
+    int grid = 1;
+    size_t lds = 0;
+    // timing: an event pair around every stage launch, resolved on query
+    bool timing = false;
+    std::vector<hipEvent_t> ev;     // start, stop, start, stop, ...
+    std::vector<int> ev_kind;
+    double time_ms = 0.0, time_ms_kind[4] = {0, 0, 0, 0};
+    int64_t time_launches = 0, launches_kind[4] = {0, 0, 0, 0};
+    // graph
+    hipGraphExec_t graph_exec = nullptr;
+    double graph_dt = 0.0;
+    int64_t graph_motion_serial = -1;
+    ~gb_solver() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- dispatch
+
+struct Launcher {
+    // launches one stage kind; returns hipError_t
+    hipError_t (*stage)(gb_solver *s, int kind, double dt, hipStream_t st);
+    hipError_t (*prepare)(gb_solver *s, double dt, hipStream_t st);
+    size_t (*lds)(int Nc, int epb);
+    int (*ops_total)(int Nc);
+};
+
+template <typename T>
+void fill_coef(gbd::StageCoef<T> &c, const gbh::SarkCoef &h, double dt) {
+    c.E1 = T(h.E[1]);
+    c.E2 = T(h.E[2]);
+    c.E3 = T(h.E[3]);
+    c.E4 = T(h.E[4]);
+    c.a10 = T(dt * h.a10);
+    c.a20 = T(dt * h.a20);
+    c.a21 = T(dt * h.a21);
+    c.a30 = T(dt * h.a30);
+    c.a32 = T(dt * h.a32);
+    c.b0 = T(dt * h.b[0]);
+    c.b1 = T(dt * h.b[1]);
+    c.b2 = T(dt * h.b[2]);
+    c.b3 = T(dt * h.b[3]);
+}
+
+// coefficients turning the five eigenvalue weights into powers of M_n:
+// inverse of V[l][p] = lambda_l^p on {-sqrt3, -1, 0, 1, sqrt3}
+void flux_vinv(double out[25]) {
+    const double lam[5] = {-std::sqrt(3.0), -1.0, 0.0, 1.0, std::sqrt(3.0)};
+    gbh::Mat V(5, 5);
+    for (int l = 0; l < 5; ++l)
+        for (int p = 0; p < 5; ++p) V(l, p) = std::pow(lam[l], p);
+    const gbh::Mat Vi = gbh::inverse(V);
+    for (int p = 0; p < 5; ++p)
+        for (int l = 0; l < 5; ++l) out[p * 5 + l] = Vi(p, l);
+}
+
+template <typename T>
+void fill_kconst(gbd::KConst<T> &k, const gb_solver *s, double dt) {
+    std::memset(&k, 0, sizeof(k));
+    fill_coef(k.cf[0], gbh::sark_coefficients(0.0), dt);
+    fill_coef(k.cf[1], gbh::sark_coefficients(-dt / s->prm.tau), dt);
+    k.c = T(s->prm.c);
+    k.inv_tau = T(1.0 / s->prm.tau);
+    const double rho0 = s->prm.precision == GB_FP32 ? s->prm.rho0 : 0.0;
+    k.rho0 = T(rho0);
+    k.flux_mode = s->prm.flux_mode;
+    double fv[25];
+    flux_vinv(fv);
+    for (int p = 0; p < 25; ++p) k.fluxV[p] = T(fv[p]);
+    for (int f = 0; f < 10; ++f) k.q_inf[f] = T(s->prm.q_inf[f] - (f == 0 ? rho0 : 0.0));
+    k.sponge = s->prm.sponge_sigma_max > 0.0;
+    k.sp_cx = s->prm.sponge_cx;
+    k.sp_cy = s->prm.sponge_cy;
+    k.sp_r0 = s->prm.sponge_r0;
+    k.sp_r1 = s->prm.sponge_r1;
+    k.sp_smax = s->prm.sponge_sigma_max;
+    k.dt = dt;
+    k.motion = s->mesh->motion;
+}
+
+// Constants for this dt and motion, uploaded in stream order when they change
+// (always outside any graph capture).
+template <typename T>
+hipError_t prepare_consts(gb_solver *s, double dt, hipStream_t st) {
+    gb_mesh *m = s->mesh;
+    if (s->kconst_dt == dt && s->kconst_motion_serial == m->motion_serial) return hipSuccess;
+    gbd::KConst<T> *hk = reinterpret_cast<gbd::KConst<T> *>(s->kconst_host.data());
+    fill_kconst(*hk, s, dt);
+    hipError_t e = hipMemcpyAsync(s->kconst.p, hk, sizeof(gbd::KConst<T>), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    s->kconst_dt = dt;
+    s->kconst_motion_serial = m->motion_serial;
+    return hipSuccess;
+}
+
+template <int DIM, int N, typename T>
+hipError_t launch_stage(gb_solver *s, int kind, double dt, hipStream_t st) {
+    gb_mesh *m = s->mesh;
+    (void)dt;
+    gbd::KArgs<T> a{};
+    a.K = m->K;
+    a.epb = s->epb;
+    a.nbatch = int((m->K + s->epb - 1) / s->epb);
+    a.Nc = s->ref.Nc;
+    int grid = std::min(s->grid, a.nbatch);
+    if (grid >= 8) grid = grid / 8 * 8;
+    a.chunk = (a.nbatch + grid - 1) / grid;
+    grid = (a.nbatch + a.chunk - 1) / a.chunk;
+    // the XCD-major remap needs a multiple of 8; surplus workgroups find no batch
+    if (grid >= 8 && grid % 8) grid = (grid + 7) / 8 * 8;
+    a.etov = m->d_etov.as<int32_t>();
+    {
+        const int64_t st = m->nv * DIM;
+        const int slot = kind == 4 ? 0 : kind;
+        a.xs = s->vstage.as<double>() + slot * st;
+        a.ws = s->wstage.as<double>() + slot * st;
+    }
+    a.vmapP = m->d_vmapP.as<int32_t>();
+    a.ops = s->ops.as<T>();
+    a.fmask = s->fmask.as<int32_t>();
+    a.Q = s->Q.as<T>();
+    a.A = s->A.as<T>();
+    a.B = s->B.as<T>();
+    a.G = s->G.as<T>();
+    a.clock = s->clock.as<double>();
+    a.kc = s->kconst.as<gbd::KConst<T>>();
+    a.err = s->err.as<int>();
+    using S = gbd::Shape<DIM, N>;
+    const dim3 block(unsigned(s->epb * S::NP));
+    const size_t lds = s->lds;
+    if (lds > 65536) {
+        const void *fns[5] = {(const void *)&gbd::stage_kernel<DIM, N, T, 0>, (const void *)&gbd::stage_kernel<DIM, N, T, 1>,
+                              (const void *)&gbd::stage_kernel<DIM, N, T, 2>, (const void *)&gbd::stage_kernel<DIM, N, T, 3>,
+                              (const void *)&gbd::stage_kernel<DIM, N, T, 4>};
+        hipError_t e = hipFuncSetAttribute(fns[kind < 4 ? kind : 4], hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    switch (kind) {
+        case 0: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 0>), dim3(grid), block, lds, st, a); break;
+        case 1: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 1>), dim3(grid), block, lds, st, a); break;
+        case 2: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 2>), dim3(grid), block, lds, st, a); break;
+        case 3: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 3>), dim3(grid), block, lds, st, a); break;
+        default: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 4>), dim3(grid), block, lds, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int DIM, int N, typename T>
+size_t lds_of(int Nc, int epb) { return gbd::lds_bytes<DIM, N, T>(Nc, epb); }
+
+template <int DIM, int N>
+int ops_total_of(int Nc) { return gbd::OpOffsets<DIM, N>::total(Nc); }
+
+template <int DIM, int N, typename T>
+Launcher make_launcher() {
+    return Launcher{&launch_stage<DIM, N, T>, &prepare_consts<T>, &lds_of<DIM, N, T>, &ops_total_of<DIM, N>};
+}
+
+bool get_launcher(int dim, int N, int prec, Launcher &L) {
+#define GB_CASE(D, NN)                                                                              \
+    if (dim == D && N == NN) {                                                                      \
+        L = prec == GB_FP64 ? make_launcher<D, NN, double>() : make_launcher<D, NN, float>();      \
+        return true;                                                                                \
+    }
+    GB_CASE(2, 1) GB_CASE(2, 2) GB_CASE(2, 3) GB_CASE(2, 4) GB_CASE(2, 5)
+    GB_CASE(3, 1) GB_CASE(3, 2) GB_CASE(3, 3)
+#undef GB_CASE
+    return false;
+}
+
+// ---------------------------------------------------------------- conversion kernels
+
+template <typename T>
+__global__ void to_state_kernel(const double *in, T *out, int64_t n, int NP, int NF, double rho0) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int field = int((idx / NP) % NF);
+    out[idx] = T(field == 0 ? in[idx] - rho0 : in[idx]);
+}
+
+template <typename T>
+__global__ void from_state_kernel(const T *in, double *out, int64_t n, int NP, int NF, double rho0) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int field = int((idx / NP) % NF);
+    out[idx] = field == 0 ? double(in[idx]) + rho0 : double(in[idx]);
+}
+
+template <typename T>
+std::vector<T> pack_ops(const gbh::RefElement &R) {
+    const int dim = R.dim, Np = R.Np, NFT = R.Nfaces * R.Nfp, Nc = R.Nc, nvert = dim + 1;
+    std::vector<T> o;
+    o.reserve(size_t(dim) * Np * Np + size_t(NFT) * Np + 2 * size_t(Np) * Nc + Np * nvert);
+    for (int a = 0; a < dim; ++a)
+        for (int j = 0; j < Np; ++j)
+            for (int i = 0; i < Np; ++i) o.push_back(T(R.D[a](i, j)));
+    for (int m = 0; m < NFT; ++m)
+        for (int i = 0; i < Np; ++i) o.push_back(T(R.LIFT(i, m)));
+    for (int j = 0; j < Np; ++j)
+        for (int k = 0; k < Nc; ++k) o.push_back(T(R.Icub(k, j)));
+    for (int k = 0; k < Nc; ++k)
+        for (int i = 0; i < Np; ++i) o.push_back(T(R.Pcub(i, k)));
+    for (int i = 0; i < Np; ++i)
+        for (int v = 0; v < nvert; ++v) o.push_back(T(R.bary(i, v)));
+    return o;
+}
+
+int n_fields(int dim) { return dim == 2 ? 6 : 10; }
+
+bool supported(int dim, int N) { return (dim == 2 && N >= 1 && N <= 5) || (dim == 3 && N >= 1 && N <= 3); }
+
+gb_status check_error_flag(gb_solver *s) {
+    int flag = 0;
+    GB_HIP(hipMemcpyAsync(&flag, s->err.p, sizeof(int), hipMemcpyDeviceToHost, s->mesh->ctx->stream));
+    GB_HIP(hipStreamSynchronize(s->mesh->ctx->stream));
+    if (flag & 1) return fail(GB_ERR_MESH, "an element was inverted (J <= 0) during stepping");
+    if (flag & 2) return fail(GB_ERR_NONPHYSICAL, "non-positive or NaN density latched on the device");
+    return GB_OK;
+}
+
+hipError_t launch_motion(gb_solver *s, double dt, hipStream_t st) {
+    gb_mesh *m = s->mesh;
+    const int blk = 256;
+    const unsigned nb = unsigned((m->nv + blk - 1) / blk);
+    if (m->dim == 2)
+        hipLaunchKernelGGL(gbd::motion_stages_kernel<2>, dim3(nb), dim3(blk), 0, st, m->nv, m->d_X.as<double>(),
+                           m->d_x.as<double>(), s->clock.as<double>(), dt, m->motion, s->vstage.as<double>(),
+                           s->wstage.as<double>());
+    else
+        hipLaunchKernelGGL(gbd::motion_stages_kernel<3>, dim3(nb), dim3(blk), 0, st, m->nv, m->d_X.as<double>(),
+                           m->d_x.as<double>(), s->clock.as<double>(), dt, m->motion, s->vstage.as<double>(),
+                           s->wstage.as<double>());
+    return hipGetLastError();
+}
+
+gb_status enqueue_step(gb_solver *s, const Launcher &L, double dt, hipStream_t st) {
+    gb_mesh *m = s->mesh;
+    GB_HIP(launch_motion(s, dt, st));
+    for (int kind = 0; kind < 4; ++kind) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (s->timing) {
+            GB_HIP(hipEventCreate(&e0));
+            GB_HIP(hipEventCreate(&e1));
+            s->ev.push_back(e0);
+            s->ev.push_back(e1);
+            s->ev_kind.push_back(kind);
+            GB_HIP(hipEventRecord(e0, st));
+        }
+        GB_HIP(L.stage(s, kind, dt, st));
+        if (s->timing) GB_HIP(hipEventRecord(e1, st));
+    }
+    const int blk = 256;
+    const unsigned nb = unsigned((m->nv + blk - 1) / blk);
+    const double *xnext = s->vstage.as<double>() + 4 * m->nv * m->dim;
+    if (m->dim == 2)
+        hipLaunchKernelGGL(gbd::finish_step_kernel<2>, dim3(nb), dim3(blk), 0, st, m->nv, m->d_x.as<double>(), xnext,
+                           s->clock.as<double>(), dt);
+    else
+        hipLaunchKernelGGL(gbd::finish_step_kernel<3>, dim3(nb), dim3(blk), 0, st, m->nv, m->d_x.as<double>(), xnext,
+                           s->clock.as<double>(), dt);
+    GB_HIP(hipGetLastError());
+    return GB_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+
+extern "C" {
+
+const char *gb_last_error(void) { return g_err.c_str(); }
+
+const char *gb_version(void) { return "gb-ale-mi355x 0.1 (gfx950)"; }
+
+gb_status gb_ctx_create(int device, void *stream, gb_ctx **out) {
+    if (!out) return fail(GB_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    GB_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(GB_ERR_ARG, "device index out of range");
+    GB_HIP(hipSetDevice(device));
+    auto c = std::make_unique<gb_ctx>();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    hipDeviceProp_t prop;
+    GB_HIP(hipGetDeviceProperties(&prop, device));
+    c->num_cu = prop.multiProcessorCount;
+    c->max_lds = prop.sharedMemPerBlock;
+    *out = c.release();
+    return GB_OK;
+}
+
+void gb_ctx_destroy(gb_ctx *ctx) { delete ctx; }
+
+gb_status gb_ctx_synchronize(gb_ctx *ctx) {
+    if (!ctx) return fail(GB_ERR_ARG, "ctx is NULL");
+    GB_HIP(hipStreamSynchronize(ctx->stream));
+    return GB_OK;
+}
+
+gb_status gb_ref_operator(int dim, int N, int cubature_degree, int which, double *out, int64_t capacity,
+                          int64_t *n_out) {
+    if (!out || !n_out) return fail(GB_ERR_ARG, "NULL output");
+    if (!((dim == 2 && N >= 1 && N <= 8) || (dim == 3 && N >= 1 && N <= 5)))
+        return fail(GB_ERR_UNSUPPORTED, "unsupported (dim, N)");
+    gbh::RefElement R;
+    try {
+        R = gbh::build_ref_element(dim, N, cubature_degree);
+    } catch (const std::exception &ex) {
+        return fail(GB_ERR_ARG, ex.what());
+    }
+    std::vector<double> v;
+    if (which >= 0 && which <= 2) {
+        if (which >= dim) return fail(GB_ERR_ARG, "no such derivative for this dimension");
+        v = R.D[which].a;
+    } else if (which == 3) {
+        v = R.LIFT.a;
+    } else if (which == 4) {
+        v = R.Icub.a;
+    } else if (which == 5) {
+        v = R.Pcub.a;
+    } else if (which == 6) {
+        v = R.r;
+    } else if (which == 7) {
+        v = R.M.a;
+    } else {
+        return fail(GB_ERR_ARG, "unknown operator id");
+    }
+    if (int64_t(v.size()) > capacity) return fail(GB_ERR_ARG, "output buffer too small");
+    std::memcpy(out, v.data(), v.size() * sizeof(double));
+    *n_out = int64_t(v.size());
+    return GB_OK;
+}
+
+gb_status gb_mesh_create(gb_ctx *ctx, int dim, int N, int64_t nv, const double *vx, int64_t K, const int32_t *etov,
+                         const double *period, const int8_t *face_tag, gb_mesh **out) {
+    if (!ctx || !vx || !etov || !out) return fail(GB_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return fail(GB_ERR_ARG, "dim must be 2 or 3");
+    if (!supported(dim, N)) return fail(GB_ERR_UNSUPPORTED, "polynomial order not built for this dimension");
+    if (nv <= 0 || K <= 0) return fail(GB_ERR_ARG, "empty mesh");
+    auto m = std::make_unique<gb_mesh>();
+    m->ctx = ctx;
+    m->dim = dim;
+    m->N = N;
+    m->K = K;
+    m->nv = nv;
+    try {
+        m->ref = gbh::build_ref_element(dim, N, 0);
+    } catch (const std::exception &ex) {
+        return fail(GB_ERR_ARG, ex.what());
+    }
+    const int nvert = dim + 1;
+    // orientation: every element positively oriented
+    for (int64_t e = 0; e < K; ++e) {
+        double G[3][3] = {{0}};
+        for (int a = 0; a < dim; ++a) {
+            const int32_t v0 = etov[e * nvert], va = etov[e * nvert + a + 1];
+            if (v0 < 0 || v0 >= nv || va < 0 || va >= nv) return fail(GB_ERR_ARG, "etov index out of range");
+            for (int d = 0; d < dim; ++d) G[d][a] = vx[int64_t(va) * dim + d] - vx[int64_t(v0) * dim + d];
+        }
+        const double J = dim == 2 ? G[0][0] * G[1][1] - G[0][1] * G[1][0]
+                                  : G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) -
+                                        G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
+                                        G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+        if (!(J > 0.0)) return fail(GB_ERR_MESH, "element " + std::to_string(e) + " is not positively oriented");
+    }
+    std::string err;
+    m->conn = gbh::build_connectivity(m->ref, nv, vx, K, etov, period, face_tag, err);
+    if (!err.empty()) return fail(GB_ERR_MESH, err);
+    m->X.assign(vx, vx + nv * dim);
+    GB_HIP(hipSetDevice(ctx->device));
+    if (m->d_etov.alloc(size_t(K) * nvert * sizeof(int32_t)) != hipSuccess ||
+        m->d_X.alloc(size_t(nv) * dim * sizeof(double)) != hipSuccess ||
+        m->d_x.alloc(size_t(nv) * dim * sizeof(double)) != hipSuccess ||
+        m->d_vmapP.alloc(m->conn.vmapP.size() * sizeof(int32_t)) != hipSuccess)
+        return fail(GB_ERR_OOM, "device allocation for the mesh failed");
+    GB_HIP(hipMemcpy(m->d_etov.p, etov, m->d_etov.bytes, hipMemcpyHostToDevice));
+    GB_HIP(hipMemcpy(m->d_X.p, vx, m->d_X.bytes, hipMemcpyHostToDevice));
+    GB_HIP(hipMemcpy(m->d_x.p, vx, m->d_x.bytes, hipMemcpyHostToDevice));
+    GB_HIP(hipMemcpy(m->d_vmapP.p, m->conn.vmapP.data(), m->d_vmapP.bytes, hipMemcpyHostToDevice));
+    m->motion.kind = 0;
+    *out = m.release();
+    return GB_OK;
+}
+
+void gb_mesh_destroy(gb_mesh *mesh) { delete mesh; }
+
+gb_status gb_mesh_sizes(const gb_mesh *m, int64_t *K, int *Np, int *NF, int *Nfp, int *Nfaces) {
+    if (!m) return fail(GB_ERR_ARG, "mesh is NULL");
+    if (K) *K = m->K;
+    if (Np) *Np = m->ref.Np;
+    if (NF) *NF = n_fields(m->dim);
+    if (Nfp) *Nfp = m->ref.Nfp;
+    if (Nfaces) *Nfaces = m->ref.Nfaces;
+    return GB_OK;
+}
+
+gb_status gb_mesh_vertices(const gb_mesh *m, double *vx) {
+    if (!m || !vx) return fail(GB_ERR_ARG, "NULL argument");
+    GB_HIP(hipSetDevice(m->ctx->device));
+    GB_HIP(hipMemcpyAsync(vx, m->d_x.p, m->d_x.bytes, hipMemcpyDeviceToHost, m->ctx->stream));
+    GB_HIP(hipStreamSynchronize(m->ctx->stream));
+    return GB_OK;
+}
+
+gb_status gb_mesh_nodes(const gb_mesh *m, double *xyz) {
+    if (!m || !xyz) return fail(GB_ERR_ARG, "NULL argument");
+    std::vector<double> x(size_t(m->nv) * m->dim);
+    gb_status s = gb_mesh_vertices(m, x.data());
+    if (s != GB_OK) return s;
+    std::vector<int32_t> etov(size_t(m->K) * (m->dim + 1));
+    GB_HIP(hipMemcpy(etov.data(), m->d_etov.p, m->d_etov.bytes, hipMemcpyDeviceToHost));
+    const int Np = m->ref.Np, dim = m->dim, nvert = dim + 1;
+    for (int64_t e = 0; e < m->K; ++e)
+        for (int d = 0; d < dim; ++d)
+            for (int i = 0; i < Np; ++i) {
+                double v = 0.0;
+                for (int a = 0; a < nvert; ++a) v += m->ref.bary(i, a) * x[size_t(etov[e * nvert + a]) * dim + d];
+                xyz[(e * dim + d) * Np + i] = v;
+            }
+    return GB_OK;
+}
+
+gb_status gb_set_motion(gb_mesh *m, const gb_motion *mo) {
+    if (!m || !mo) return fail(GB_ERR_ARG, "NULL argument");
+    if (mo->kind < 0 || mo->kind > 3) return fail(GB_ERR_ARG, "unknown motion kind");
+    if (mo->kind == GB_MOTION_TRIPLE_PRODUCT_3D && m->dim != 3) return fail(GB_ERR_ARG, "3D motion on a 2D mesh");
+    if ((mo->kind == GB_MOTION_SIN_PRODUCT_2D || mo->kind == GB_MOTION_PLUNGE_BLEND_2D) && m->dim != 2)
+        return fail(GB_ERR_ARG, "2D motion on a 3D mesh");
+    m->motion.kind = mo->kind;
+    for (int i = 0; i < 8; ++i) m->motion.p[i] = mo->p[i];
+    ++m->motion_serial;
+    return GB_OK;
+}
+
+gb_status gb_solver_footprint(const gb_mesh *m, const gb_params *p, size_t *bytes) {
+    if (!m || !p || !bytes) return fail(GB_ERR_ARG, "NULL argument");
+    const size_t es = p->precision == GB_FP32 ? 4 : 8;
+    *bytes = 4 * size_t(m->K) * n_fields(m->dim) * m->ref.Np * es;
+    return GB_OK;
+}
+
+gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
+    if (!m || !p || !out) return fail(GB_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (!(p->c > 0.0) || !(p->tau > 0.0)) return fail(GB_ERR_ARG, "c and tau must be positive");
+    if (p->precision != GB_FP64 && p->precision != GB_FP32) return fail(GB_ERR_ARG, "unknown precision");
+    if (p->flux_mode != GB_FLUX_SPLIT && p->flux_mode != GB_FLUX_RELATIVE) return fail(GB_ERR_ARG, "unknown flux mode");
+    auto s = std::make_unique<gb_solver>();
+    s->mesh = m;
+    s->prm = *p;
+    s->NF = n_fields(m->dim);
+    try {
+        s->ref = gbh::build_ref_element(m->dim, m->N, p->cubature_degree);
+    } catch (const std::exception &ex) {
+        return fail(GB_ERR_ARG, ex.what());
+    }
+    Launcher L;
+    if (!get_launcher(m->dim, m->N, p->precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel for this configuration");
+    s->elem_bytes = p->precision == GB_FP32 ? 4 : 8;
+    const int Np = s->ref.Np;
+    // elements per workgroup: fill up to 256 threads within the LDS budget
+    const size_t budget = std::min<size_t>(m->ctx->max_lds, 65536);
+    int epb = std::max(1, 256 / Np);
+    while (epb > 1 && L.lds(s->ref.Nc, epb) > budget) --epb;
+    size_t need = L.lds(s->ref.Nc, epb);
+    if (need > m->ctx->max_lds) return fail(GB_ERR_UNSUPPORTED, "reference operators exceed the LDS of one workgroup");
+    s->epb = epb;
+    s->lds = need;
+    s->kconst_host.assign(std::max(sizeof(gbd::KConst<double>), sizeof(gbd::KConst<float>)), 0);
+    s->grid = m->ctx->num_cu * 8;
+    GB_HIP(hipSetDevice(m->ctx->device));
+    const size_t n = size_t(m->K) * s->NF * Np;
+    if (s->Q.alloc(n * s->elem_bytes) != hipSuccess || s->A.alloc(n * s->elem_bytes) != hipSuccess ||
+        s->B.alloc(n * s->elem_bytes) != hipSuccess || s->G.alloc(n * s->elem_bytes) != hipSuccess ||
+        s->clock.alloc(2 * sizeof(double)) != hipSuccess || s->err.alloc(sizeof(int)) != hipSuccess ||
+        s->kconst.alloc(std::max(sizeof(gbd::KConst<double>), sizeof(gbd::KConst<float>))) != hipSuccess ||
+        s->vstage.alloc(5 * size_t(m->nv) * m->dim * sizeof(double)) != hipSuccess ||
+        s->wstage.alloc(4 * size_t(m->nv) * m->dim * sizeof(double)) != hipSuccess)
+        return fail(GB_ERR_OOM, "device allocation for the solver state failed");
+    if (p->precision == GB_FP64) {
+        auto o = pack_ops<double>(s->ref);
+        if (s->ops.alloc(o.size() * sizeof(double)) != hipSuccess) return fail(GB_ERR_OOM, "ops");
+        GB_HIP(hipMemcpy(s->ops.p, o.data(), s->ops.bytes, hipMemcpyHostToDevice));
+    } else {
+        auto o = pack_ops<float>(s->ref);
+        if (s->ops.alloc(o.size() * sizeof(float)) != hipSuccess) return fail(GB_ERR_OOM, "ops");
+        GB_HIP(hipMemcpy(s->ops.p, o.data(), s->ops.bytes, hipMemcpyHostToDevice));
+    }
+    if (s->fmask.alloc(s->ref.fmask.size() * sizeof(int32_t)) != hipSuccess) return fail(GB_ERR_OOM, "fmask");
+    std::vector<int32_t> fm(s->ref.fmask.begin(), s->ref.fmask.end());
+    GB_HIP(hipMemcpy(s->fmask.p, fm.data(), s->fmask.bytes, hipMemcpyHostToDevice));
+    GB_HIP(hipMemset(s->err.p, 0, sizeof(int)));
+    double clk[2] = {0.0, 0.0};
+    GB_HIP(hipMemcpy(s->clock.p, clk, sizeof(clk), hipMemcpyHostToDevice));
+    ++m->solvers;
+    *out = s.release();
+    return GB_OK;
+}
+
+void gb_solver_destroy(gb_solver *s) {
+    if (!s) return;
+    if (s->mesh) --s->mesh->solvers;
+    delete s;
+}
+
+gb_status gb_state_set(gb_solver *s, const double *q, double t0) {
+    if (!s || !q) return fail(GB_ERR_ARG, "NULL argument");
+    gb_mesh *m = s->mesh;
+    GB_HIP(hipSetDevice(m->ctx->device));
+    const int64_t n = m->K * s->NF * s->ref.Np;
+    DevBuf tmp;
+    if (tmp.alloc(size_t(n) * sizeof(double)) != hipSuccess) return fail(GB_ERR_OOM, "staging buffer");
+    hipStream_t st = m->ctx->stream;
+    GB_HIP(hipMemcpyAsync(tmp.p, q, size_t(n) * sizeof(double), hipMemcpyHostToDevice, st));
+    const unsigned nb = unsigned((n + 255) / 256);
+    const double rho0 = s->prm.precision == GB_FP32 ? s->prm.rho0 : 0.0;
+    if (s->prm.precision == GB_FP64)
+        hipLaunchKernelGGL(to_state_kernel<double>, dim3(nb), dim3(256), 0, st, tmp.as<double>(), s->Q.as<double>(), n,
+                           s->ref.Np, s->NF, 0.0);
+    else
+        hipLaunchKernelGGL(to_state_kernel<float>, dim3(nb), dim3(256), 0, st, tmp.as<double>(), s->Q.as<float>(), n,
+                           s->ref.Np, s->NF, rho0);
+    GB_HIP(hipGetLastError());
+    double clk[2] = {t0, 0.0};
+    GB_HIP(hipMemcpyAsync(s->clock.p, clk, sizeof(clk), hipMemcpyHostToDevice, st));
+    GB_HIP(hipMemsetAsync(s->err.p, 0, sizeof(int), st));
+    GB_HIP(hipStreamSynchronize(st));
+    s->t = t0;
+    s->step = 0;
+    s->has_state = true;
+    return GB_OK;
+}
+
+gb_status gb_state_get(gb_solver *s, double *q, double *t, int64_t *step) {
+    if (!s) return fail(GB_ERR_ARG, "NULL solver");
+    if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
+    gb_mesh *m = s->mesh;
+    GB_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t st = m->ctx->stream;
+    gb_status es = check_error_flag(s);
+    if (q) {
+        const int64_t n = m->K * s->NF * s->ref.Np;
+        DevBuf tmp;
+        if (tmp.alloc(size_t(n) * sizeof(double)) != hipSuccess) return fail(GB_ERR_OOM, "staging buffer");
+        const unsigned nb = unsigned((n + 255) / 256);
+        if (s->prm.precision == GB_FP64)
+            hipLaunchKernelGGL(from_state_kernel<double>, dim3(nb), dim3(256), 0, st, s->Q.as<double>(),
+                               tmp.as<double>(), n, s->ref.Np, s->NF, 0.0);
+        else
+            hipLaunchKernelGGL(from_state_kernel<float>, dim3(nb), dim3(256), 0, st, s->Q.as<float>(),
+                               tmp.as<double>(), n, s->ref.Np, s->NF, s->prm.rho0);
+        GB_HIP(hipGetLastError());
+        GB_HIP(hipMemcpyAsync(q, tmp.p, size_t(n) * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    double clk[2];
+    GB_HIP(hipMemcpyAsync(clk, s->clock.p, sizeof(clk), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipStreamSynchronize(st));
+    if (t) *t = clk[0];
+    if (step) *step = int64_t(clk[1]);
+    return es;
+}
+
+gb_status gb_rhs(gb_solver *s, const double *q, double *F) {
+    if (!s || !q || !F) return fail(GB_ERR_ARG, "NULL argument");
+    gb_mesh *m = s->mesh;
+    Launcher L;
+    if (!get_launcher(m->dim, m->N, s->prm.precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel");
+    GB_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t st = m->ctx->stream;
+    const int64_t n = m->K * s->NF * s->ref.Np;
+    DevBuf dq, din, dout;
+    if (dq.alloc(size_t(n) * sizeof(double)) != hipSuccess || din.alloc(size_t(n) * s->elem_bytes) != hipSuccess ||
+        dout.alloc(size_t(n) * s->elem_bytes) != hipSuccess)
+        return fail(GB_ERR_OOM, "rhs buffers");
+    GB_HIP(hipMemcpyAsync(dq.p, q, size_t(n) * sizeof(double), hipMemcpyHostToDevice, st));
+    const unsigned nb = unsigned((n + 255) / 256);
+    const double rho0 = s->prm.precision == GB_FP32 ? s->prm.rho0 : 0.0;
+    if (s->prm.precision == GB_FP64)
+        hipLaunchKernelGGL(to_state_kernel<double>, dim3(nb), dim3(256), 0, st, dq.as<double>(), din.as<double>(), n,
+                           s->ref.Np, s->NF, 0.0);
+    else
+        hipLaunchKernelGGL(to_state_kernel<float>, dim3(nb), dim3(256), 0, st, dq.as<double>(), din.as<float>(), n,
+                           s->ref.Np, s->NF, rho0);
+    GB_HIP(hipGetLastError());
+    {
+        hipError_t pe = L.prepare(s, 0.0, st);
+        if (pe != hipSuccess) return fail(GB_ERR_DEVICE, std::string("constants upload: ") + hipGetErrorString(pe));
+    }
+    {
+        hipError_t me = launch_motion(s, 0.0, st);
+        if (me != hipSuccess) return fail(GB_ERR_DEVICE, std::string("motion: ") + hipGetErrorString(me));
+    }
+    // point the state slots at the scratch buffers for one RHS-only launch
+    std::swap(s->Q.p, din.p);
+    std::swap(s->A.p, dout.p);
+    hipError_t le = L.stage(s, 4, 0.0, st);
+    std::swap(s->Q.p, din.p);
+    std::swap(s->A.p, dout.p);
+    if (le != hipSuccess) return fail(GB_ERR_DEVICE, std::string("rhs launch: ") + hipGetErrorString(le));
+    if (s->prm.precision == GB_FP64)
+        hipLaunchKernelGGL(from_state_kernel<double>, dim3(nb), dim3(256), 0, st, dout.as<double>(), dq.as<double>(), n,
+                           s->ref.Np, s->NF, 0.0);
+    else
+        hipLaunchKernelGGL(from_state_kernel<float>, dim3(nb), dim3(256), 0, st, dout.as<float>(), dq.as<double>(), n,
+                           s->ref.Np, s->NF, 0.0);
+    GB_HIP(hipGetLastError());
+    GB_HIP(hipMemcpyAsync(F, dq.p, size_t(n) * sizeof(double), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipStreamSynchronize(st));
+    return check_error_flag(s);
+}
+
+gb_status gb_sark_step(gb_solver *s, double dt, int64_t nsteps) {
+    if (!s) return fail(GB_ERR_ARG, "NULL solver");
+    if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
+    if (!(dt > 0.0) || nsteps < 0) return fail(GB_ERR_ARG, "dt must be positive and nsteps >= 0");
+    gb_mesh *m = s->mesh;
+    Launcher L;
+    if (!get_launcher(m->dim, m->N, s->prm.precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel");
+    GB_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t st = m->ctx->stream;
+    GB_HIP(L.prepare(s, dt, st));
+    for (int64_t k = 0; k < nsteps; ++k) {
+        gb_status r = enqueue_step(s, L, dt, st);
+        if (r != GB_OK) return r;
+    }
+    s->step += nsteps;
+    return GB_OK;
+}
+
+gb_status gb_sark_step_graph(gb_solver *s, double dt, int64_t nsteps) {
+    if (!s) return fail(GB_ERR_ARG, "NULL solver");
+    if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
+    if (!(dt > 0.0) || nsteps < 0) return fail(GB_ERR_ARG, "dt must be positive and nsteps >= 0");
+    gb_mesh *m = s->mesh;
+    Launcher L;
+    if (!get_launcher(m->dim, m->N, s->prm.precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel");
+    GB_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t st = m->ctx->stream;
+    GB_HIP(L.prepare(s, dt, st));
+    if (!s->graph_exec || s->graph_dt != dt || s->graph_motion_serial != m->motion_serial) {
+        if (s->graph_exec) {
+            GB_HIP(hipGraphExecDestroy(s->graph_exec));
+            s->graph_exec = nullptr;
+        }
+        // capture on a private stream (the legacy default stream cannot be captured)
+        hipStream_t cap;
+        GB_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        const bool timing = s->timing;
+        s->timing = false;
+        hipGraph_t g;
+        GB_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        gb_status r = enqueue_step(s, L, dt, cap);
+        hipError_t ce = hipStreamEndCapture(cap, &g);
+        s->timing = timing;
+        (void)hipStreamDestroy(cap);
+        if (r != GB_OK) return r;
+        if (ce != hipSuccess) return fail(GB_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(GB_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        s->graph_dt = dt;
+        s->graph_motion_serial = m->motion_serial;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) GB_HIP(hipGraphLaunch(s->graph_exec, st));
+    s->step += nsteps;
+    return GB_OK;
+}
+
+static gb_status resolve_events(gb_solver *s) {
+    if (s->ev.empty()) return GB_OK;
+    GB_HIP(hipEventSynchronize(s->ev.back()));
+    for (size_t p = 0; p + 1 < s->ev.size(); p += 2) {
+        float ms = 0.f;
+        GB_HIP(hipEventElapsedTime(&ms, s->ev[p], s->ev[p + 1]));
+        const int kind = s->ev_kind[p / 2];
+        s->time_ms += ms;
+        s->time_ms_kind[kind] += ms;
+        ++s->time_launches;
+        ++s->launches_kind[kind];
+    }
+    for (auto e : s->ev) (void)hipEventDestroy(e);
+    s->ev.clear();
+    s->ev_kind.clear();
+    return GB_OK;
+}
+
+gb_status gb_solver_time_stages(gb_solver *s, int enable) {
+    if (!s) return fail(GB_ERR_ARG, "NULL solver");
+    gb_status r = resolve_events(s);
+    if (r != GB_OK) return r;
+    s->timing = enable != 0;
+    s->time_ms = 0.0;
+    s->time_launches = 0;
+    for (int k = 0; k < 4; ++k) {
+        s->time_ms_kind[k] = 0.0;
+        s->launches_kind[k] = 0;
+    }
+    return GB_OK;
+}
+
+gb_status gb_solver_stage_time(gb_solver *s, double *avg_ms, int64_t *launches) {
+    if (!s) return fail(GB_ERR_ARG, "NULL solver");
+    gb_status r = resolve_events(s);
+    if (r != GB_OK) return r;
+    if (avg_ms) *avg_ms = s->time_launches ? s->time_ms / double(s->time_launches) : 0.0;
+    if (launches) *launches = s->time_launches;
+    return GB_OK;
+}
+
+gb_status gb_solver_stage_time_by_kind(gb_solver *s, double *avg_ms4) {
+    if (!s || !avg_ms4) return fail(GB_ERR_ARG, "NULL argument");
+    gb_status r = resolve_events(s);
+    if (r != GB_OK) return r;
+    for (int k = 0; k < 4; ++k) avg_ms4[k] = s->launches_kind[k] ? s->time_ms_kind[k] / double(s->launches_kind[k]) : 0.0;
+    return GB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,252 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every input comes from the seeded generators in ``workloads`` (and the
+oracle's equilibrium map); expected values come from the oracle only.
+Tolerances: FP64 1e-12 relative per field; FP32 (perturbation storage
+q1 - rho0) 1e-5 relative on the velocity, looser bounds stated per test for
+raw right-hand sides.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gbsystem as gb
+from oracle.mesh import Mesh
+from oracle.motion import Motion
+from oracle.rhs import Params, rhs as oracle_rhs
+from oracle.solver import Solver
+from workloads import make_case, kuhn_cube, ogrid_airfoil
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_2607_00199_amd")
+from paper_2607_00199_amd import _lib as L  # noqa: E402
+from paper_2607_00199_amd.session import Session  # noqa: E402
+
+
+def _oracle_for(case, mode="split", **kw):
+    mesh = Mesh(case.dim, case.N, case.vx, case.etov, case.period, face_tag=case.face_tag)
+    mot = dict(case.motion)
+    kind = mot.pop("kind")
+    return Solver(mesh, Params(c=case.c, tau=case.tau, flux_mode=mode, **kw), Motion(kind, **mot))
+
+
+def _state(osolver, case, perturb=0.0, seed=0):
+    X = osolver.node_coords()
+    rho, u = case.macroscopic(X)
+    q = gb.equilibrium(case.dim, rho, u, case.c).transpose(1, 0, 2).copy()
+    if case.init == "decay":
+        q[:, case.dim + 1:] += case.extra["delta"]
+    if perturb:
+        rng = np.random.default_rng(seed)
+        q += perturb * rng.standard_normal(q.shape) * np.abs(q).max(axis=(0, 2))[None, :, None]
+    return q
+
+
+def _rel(a, b):
+    """Largest per-field relative L2 difference."""
+    out = 0.0
+    for f in range(a.shape[1]):
+        nrm = np.linalg.norm(b[:, f])
+        if nrm > 0:
+            out = max(out, np.linalg.norm(a[:, f] - b[:, f]) / nrm)
+    return out
+
+
+def test_library_is_native():
+    assert L.load() is not None
+    assert "gfx950" in L.gb_version()
+
+
+@pytest.mark.parametrize("name,kw", [("C1", {}), ("C2_small", {}), ("C3", {"n": 3})])
+def test_nodes_match_oracle(name, kw):
+    case = make_case(name, **kw)
+    s = Session(case)
+    o = _oracle_for(case)
+    assert np.abs(s.nodes() - o.node_coords()).max() < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("mode,flux", [("split", L.GB_FLUX_SPLIT), ("relative", L.GB_FLUX_RELATIVE)])
+def test_rhs_parity_fp64_2d(mode, flux):
+    case = make_case("C1", n=8)
+    s = Session(case, flux_mode=flux)
+    o = _oracle_for(case, mode)
+    q = _state(o, case, perturb=1e-3)
+    Fg = s.rhs(q)
+    Fo = o.rhs_now(q)
+    assert _rel(Fg, Fo) < 1e-12
+    s.close()
+
+
+def test_rhs_parity_fp64_2d_moving_time():
+    """Right-hand side at t > 0 (nonzero grid velocity) after the state was
+    set with that time: exercises the ALE terms."""
+    case = make_case("C1", n=8)
+    s = Session(case)
+    o = _oracle_for(case)
+    q = _state(o, case, perturb=1e-3, seed=3)
+    t0 = 0.13
+    s.set_state(q, t0)
+    o.set_state(q, t0)
+    Fg = s.rhs(q)
+    Fo = o.rhs_now(q)
+    assert _rel(Fg, Fo) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_rhs_parity_fp64_orders(N):
+    case = make_case("C2_small", n=6, N=N)
+    s = Session(case)
+    o = _oracle_for(case)
+    q = _state(o, case, perturb=1e-3, seed=N)
+    assert _rel(s.rhs(q), o.rhs_now(q)) < 1e-12
+    s.close()
+
+
+def test_rhs_parity_fp32_2d():
+    case = make_case("C2_small", n=8)
+    s = Session(case, precision=L.GB_FP32)
+    o = _oracle_for(case)
+    q = _state(o, case, perturb=1e-4, seed=5)
+    Fg, Fo = s.rhs(q), o.rhs_now(q)
+    # FP32 arithmetic on O(1e-1) momenta and O(1e-3) stresses: relative to the
+    # largest entry of each field
+    for f in range(6):
+        assert np.abs(Fg[:, f] - Fo[:, f]).max() < 2e-5 * np.abs(Fo[:, f]).max(), f
+    s.close()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_rhs_parity_fp64_3d(N):
+    case = make_case("C3", n=3, N=N)
+    s = Session(case)
+    o = _oracle_for(case)
+    q = _state(o, case, perturb=1e-3, seed=N)
+    s.set_state(q, 2.0)
+    o.set_state(q, 2.0)
+    assert _rel(s.rhs(q), o.rhs_now(q)) < 1e-12
+    s.close()
+
+
+def test_rhs_parity_boundaries_and_sponge():
+    """O-grid with wall and far-field faces and the sponge layer (stand-ins,
+    parity against the oracle's stand-ins only)."""
+    vx, etov, per, tag = ogrid_airfoil(6, 24, radius=6.0)
+    case = make_case("C4")
+    case.vx, case.etov, case.period, case.face_tag = vx, etov, per, tag
+    case.motion = dict(case.motion, r_in=1.0, r_out=4.0)
+    q_inf = gb.equilibrium(2, np.array(1.0), [np.array(0.1), np.array(0.0)], 1.0)
+    sponge = (0.5, 0.0, 4.5, 6.0, 2.0)
+    s = Session(case, q_inf=q_inf, sponge=sponge)
+    o = _oracle_for(case, q_inf=q_inf, sponge=sponge)
+    q = _state(o, case, perturb=1e-3, seed=9)
+    s.set_state(q, 0.3)
+    o.set_state(q, 0.3)
+    assert _rel(s.rhs(q), o.rhs_now(q)) < 1e-12
+    s.close()
+
+
+def _run_both(case, nsteps, precision=L.GB_FP64, mode="split", graph=False):
+    flux = L.GB_FLUX_SPLIT if mode == "split" else L.GB_FLUX_RELATIVE
+    s = Session(case, precision=precision, flux_mode=flux)
+    o = _oracle_for(case, mode)
+    q0 = _state(o, case)
+    s.set_state(q0)
+    o.set_state(q0)
+    s.step(case.dt, nsteps, graph=graph)
+    qg, t, step = s.get_state()
+    o.run(case.dt, nsteps)
+    xg = L.gb_mesh_vertices(s.mesh, case.vx.shape[0], case.dim)
+    s.close()
+    return qg, o, t, step, xg
+
+
+def test_sark_c1_full_fp64():
+    """The 2D moving Taylor-Green configuration: 512 triangles, N=3, 200 SARK
+    steps; GPU FP64 within 1e-12 of the oracle."""
+    case = make_case("C1")
+    qg, o, t, step, xg = _run_both(case, case.nsteps)
+    assert step == case.nsteps and abs(t - o.t) < 1e-14
+    assert np.abs(xg - o.x).max() < 1e-14
+    assert _rel(qg, o.q) < 1e-12
+
+
+def test_sark_relative_flux_fp64():
+    case = make_case("C1", n=8)
+    qg, o, *_ = _run_both(case, 40, mode="relative")
+    assert _rel(qg, o.q) < 1e-12
+
+
+def test_graph_replay_matches_eager():
+    case = make_case("C1", n=8)
+    a = Session(case)
+    b = Session(case)
+    q0 = a.initial_state()
+    a.set_state(q0)
+    b.set_state(q0)
+    for _ in range(3):
+        a.step(case.dt, 5)
+        b.step(case.dt, 5, graph=True)
+        qa, ta, _ = a.get_state()
+        qb, tb, _ = b.get_state()
+        assert np.array_equal(qa, qb) and ta == tb
+    a.close()
+    b.close()
+
+
+def test_free_stream_gpu():
+    case = make_case("C1_freestream")
+    s = Session(case)
+    q0 = s.initial_state()
+    s.set_state(q0)
+    s.step(case.dt, 100)
+    q, *_ = s.get_state()
+    assert np.abs(q - q0).max() < 1e-14
+    s.close()
+
+
+def test_decay_gpu():
+    case = make_case("C1_decay")
+    s = Session(case)
+    q0 = s.initial_state()
+    s.set_state(q0)
+    s.step(case.dt, 10)
+    q, t, _ = s.get_state()
+    exact = q0.copy()
+    exact[:, 3:] = (q0[:, 3:] - case.extra["delta"]) + case.extra["delta"] * math.exp(-t / case.tau)
+    assert np.abs(q - exact).max() < 1e-14
+    s.close()
+
+
+def test_sark_3d_few_steps_fp64():
+    case = make_case("C3", n=3, N=2)
+    qg, o, *_ = _run_both(case, 4)
+    assert _rel(qg, o.q) < 1e-12
+
+
+def test_fp32_velocity_short_run():
+    """FP32 with perturbation storage against the FP64 oracle: velocity
+    within 1e-5 relative after 200 steps of the 32x32 copy of the 2D TGV."""
+    case = make_case("C2_small")
+    qg, o, *_ = _run_both(case, 200, precision=L.GB_FP32)
+    ug = gb.velocity(2, qg.transpose(1, 0, 2), case.c)
+    uo = gb.velocity(2, o.q.transpose(1, 0, 2), case.c)
+    assert np.linalg.norm(ug - uo) / np.linalg.norm(uo) < 1e-5
+
+
+def test_error_latch_nonphysical():
+    """A non-positive density set from the host is latched by the kernel and
+    reported by the next synchronising call."""
+    case = make_case("C1", n=4)
+    s = Session(case)
+    q = s.initial_state()
+    q[0, 0, :] = -1.0
+    s.set_state(q)
+    s.step(case.dt, 1)
+    with pytest.raises(L.GbError) as ei:
+        s.get_state()
+    assert ei.value.status == L.GB_ERR_NONPHYSICAL
+    s.close()
