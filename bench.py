@@ -1,0 +1,194 @@
+"""Benchmark of the fused ALE Galerkin-Boltzmann SARK-4 path on one MI355X.
+
+Workload: the 2D moving Taylor-Green vortex at scale -- a periodic square of
+256 x 256 quads split into 131072 triangles, N = 4 (15 nodes), 6 fields,
+sinusoidal mesh motion, Re 1000, Ma 0.05; FP32 with perturbation storage
+q1 - rho0 (the reported value) and FP64 (reported beside it).
+
+One step = one SARK-4 step: the per-vertex motion kernel, the four fused
+stage kernels (geometry, volume, upwind surface, cubature relaxation, stage
+combination) and the end-of-step vertex update.  Inputs are resident in HBM
+before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  The metric is GDOF-stage/s = K_el * Np * NF * 4 *
+steps / seconds / 1e9.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_launch(K: int, Np: int, NF: int, dim: int, elem_bytes: int) -> float:
+    """Bytes the stage kernel must move per launch: 15 state passes per
+    SARK-4 step (3.75 per stage) of K*Np*NF values, plus per element the
+    stage vertex coordinates ((dim+1)*dim FP64), the element's vertex ids and
+    its face-neighbour ids ((dim+1) + (dim+1) int32)."""
+    state = 3.75 * K * Np * NF * elem_bytes
+    geom = K * ((dim + 1) * dim * 8 + 2 * (dim + 1) * 4)
+    return state + geom
+
+
+def run_gpu(precision_name: str, steps: int, warmup: int, n: int):
+    import numpy as np
+    import torch
+
+    from paper_2607_00199_amd import _lib as L
+    from paper_2607_00199_amd.session import Session
+    from workloads import make_case
+
+    prec = L.GB_FP32 if precision_name == "f32" else L.GB_FP64
+    case = make_case("C2", n=n)
+    stream = torch.cuda.current_stream().cuda_stream
+    s = Session(case, precision=prec, device=0, stream=stream)
+    q0 = s.initial_state()
+    s.set_state(q0)
+    s.step(case.dt, warmup)
+    torch.cuda.synchronize()
+    L.gb_solver_time_stages(s.solver, True)
+    t0 = time.perf_counter()
+    s.step(case.dt, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    avg_ms, launches = L.gb_solver_stage_time(s.solver)
+    by_kind = L.gb_solver_stage_time_by_kind(s.solver)
+    L.gb_solver_time_stages(s.solver, False)
+    q, t, nstep = s.get_state()
+    # graph replay of the same step, timed separately
+    s2 = Session(case, precision=prec, device=0, stream=stream)
+    s2.set_state(q0)
+    s2.step(case.dt, warmup, graph=True)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    s2.step(case.dt, steps, graph=True)
+    torch.cuda.synchronize()
+    gel = time.perf_counter() - g0
+    s2.close()
+    K, Np, NF = s.K, s.Np, s.NF
+    s.close()
+    dof = K * Np * NF
+    return {
+        "case": case, "K": K, "Np": Np, "NF": NF, "dof": dof, "seconds": el, "graph_seconds": gel,
+        "gdof_stage_s": dof * 4 * steps / el / 1e9,
+        "graph_gdof_stage_s": dof * 4 * steps / gel / 1e9,
+        "stage_avg_ms": avg_ms, "stage_launches": launches, "stage_ms_by_kind": [float(x) for x in by_kind],
+        "q": q, "t": t, "steps_done": nstep,
+    }
+
+
+def cpu_baseline(seconds_budget: float = 15.0):
+    """Time the oracle (unchanged) on a bounded sample of the workload: the
+    32 x 32 copy of the same configuration (2048 triangles, N = 4), as many
+    SARK-4 steps as fit the budget, in a child process pinned to one thread."""
+    code = r"""
+import os, sys, time, json
+sys.path.insert(0, %r)
+from workloads import make_case
+from oracle.mesh import Mesh
+from oracle.rhs import Params
+from oracle.solver import Solver
+from oracle.motion import Motion
+from oracle import gbsystem as gb
+case = make_case("C2_small")
+mot = dict(case.motion); kind = mot.pop("kind")
+s = Solver(Mesh(2, case.N, case.vx, case.etov, case.period), Params(c=case.c, tau=case.tau), Motion(kind, **mot))
+X = s.node_coords(); rho, u = case.macroscopic(X)
+s.set_state(gb.equilibrium(2, rho, u, case.c).transpose(1, 0, 2).copy())
+s.step(case.dt)
+n = 0; t0 = time.perf_counter()
+while time.perf_counter() - t0 < %f:
+    s.step(case.dt); n += 1
+el = time.perf_counter() - t0
+dof = case.K * s.mesh.ref.Np * 6
+print(json.dumps({"steps": n, "seconds": el, "K": case.K, "dof": dof, "gdof_stage_s": dof * 4 * n / el / 1e9}))
+""" % (ROOT, seconds_budget)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="quads per side (256 = the configuration)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    r32 = run_gpu("f32", args.steps, args.warmup, args.n)
+    r64 = None if args.no_fp64 else run_gpu("f64", args.steps, args.warmup, args.n)
+
+    case = r32["case"]
+    K, Np, NF = r32["K"], r32["Np"], r32["NF"]
+    bytes_launch = algorithmic_bytes_per_launch(K, Np, NF, 2, 4)
+    achieved = bytes_launch / (r32["stage_avg_ms"] * 1e-3) / 1e9
+    traffic = None
+    out = {
+        "metric": "GDOF-stage/s (FP32 perturbation storage; FP64 beside it)",
+        "value": round(r32["gdof_stage_s"], 3),
+        "unit": "GDOF-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["seconds"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D moving Taylor-Green vortex, periodic {args.n}x{args.n} quads -> {K} triangles, "
+                               f"N={case.N} (Np={Np}), 6 fields, sin-product mesh motion A=0.05 T=1, Re 1000, Ma 0.05, "
+                               f"dt={case.dt:.4e} (CFL 0.5), FP32 storage q1-rho0",
+                   "K": K, "N": case.N, "dof": r32["dof"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "stage_kernel<2,4,float,*> (4 stage kinds averaged)",
+                     "bytes_per_launch": bytes_launch, "avg_launch_ms": round(r32["stage_avg_ms"], 5),
+                     "launches": r32["stage_launches"],
+                     "avg_ms_by_stage": [round(x, 5) for x in r32["stage_ms_by_kind"]]},
+        "graph_replay_gdof_stage_s": round(r32["graph_gdof_stage_s"], 3),
+    }
+    if r64 is not None:
+        b64 = algorithmic_bytes_per_launch(K, Np, NF, 2, 8)
+        a64 = b64 / (r64["stage_avg_ms"] * 1e-3) / 1e9
+        u32 = r32["q"][:, 1:3] / r32["q"][:, 0:1]
+        u64 = r64["q"][:, 1:3] / r64["q"][:, 0:1]
+        out["fp64"] = {"gdof_stage_s": round(r64["gdof_stage_s"], 3),
+                       "graph_gdof_stage_s": round(r64["graph_gdof_stage_s"], 3),
+                       "ms_per_step": round(r64["seconds"] / args.steps * 1e3, 4),
+                       "stage_avg_ms": round(r64["stage_avg_ms"], 5),
+                       "achieved_GBs": round(a64, 1), "frac": round(a64 / HBM_PEAK_GBS, 4)}
+        out["fp32_vs_fp64_velocity_rel_err"] = float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64))
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline()
+        out["cpu_baseline"] = {"value": round(cb.get("gdof_stage_s", float("nan")), 6), "unit": "GDOF-stage/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"FP64 numpy oracle, 32x32-quad copy of the workload (K={cb.get('K')}, N=4), "
+                                         f"{cb.get('steps')} SARK-4 steps in {cb.get('seconds', 0):.1f} s, one thread"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

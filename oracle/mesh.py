@@ -65,53 +65,61 @@ class Mesh:
         if np.any(J <= 0):
             raise ValueError("mesh has non-positively oriented elements")
         self.nodes_x = np.einsum("nv,kvd->knd", ref.bary, P)
-        # face matching by wrapped, sorted vertex coordinates
+        # face matching: key = wrapped face centroid + wrapped sorted vertex
+        # coordinates (on meshes only two cells per period two different faces
+        # can share a wrapped vertex set, never a wrapped centroid)
         scale = max(float(np.ptp(self.vx, axis=0).max()), 1.0)
-        keys = {}
         nf = ref.Nfaces
-        self.etoe = np.tile(np.arange(self.K)[:, None], (1, nf))
-        self.etof = np.tile(np.arange(nf)[None, :], (self.K, 1))
-        matched = np.zeros((self.K, nf), bool)
-        for e in range(self.K):
-            for f, fv in enumerate(ref.faces):
-                # wrapped centroid plus wrapped vertex set: on meshes only two
-                # cells per period two different faces can share a wrapped
-                # vertex set, never a wrapped centroid
-                cen = _wrap(P[e, list(fv)].mean(axis=0), lo, self.period)
-                pts = _wrap(P[e, list(fv)], lo, self.period)
-                key = (tuple(np.round(cen / scale * 1e8).astype(np.int64)),
-                       tuple(sorted(tuple(np.round(p / scale * 1e8).astype(np.int64)) for p in pts)))
-                if key in keys:
-                    e2, f2 = keys.pop(key)
-                    self.etoe[e, f], self.etof[e, f] = e2, f2
-                    self.etoe[e2, f2], self.etof[e2, f2] = e, f
-                    matched[e, f] = matched[e2, f2] = True
-                else:
-                    keys[key] = (e, f)
-        self.face_tag = np.zeros((self.K, nf), np.int8)
+        K = self.K
+        fverts = np.array(ref.faces)                              # [nf, dim]
+        FP = P[:, fverts]                                         # [K, nf, dim(verts), dim]
+        cen = _wrap(FP.mean(axis=2), lo, self.period)             # [K, nf, dim]
+        vw = _wrap(FP, lo, self.period)
+        qv = np.round(vw / scale * 1e8).astype(np.int64)          # [K, nf, nv_f, dim]
+        # sort the vertices of each face lexicographically (stable passes,
+        # least significant coordinate first)
+        keys_v = qv.reshape(K * nf, dim, dim)                     # [face, vertex, coord]
+        perm = np.tile(np.arange(dim), (K * nf, 1))
+        for d in reversed(range(dim)):
+            col = np.take_along_axis(keys_v[:, :, d], perm, axis=1)
+            perm = np.take_along_axis(perm, np.argsort(col, axis=1, kind="stable"), axis=1)
+        srt = np.take_along_axis(keys_v, perm[:, :, None], axis=1).reshape(K * nf, dim * dim)
+        keys = np.concatenate([np.round(cen / scale * 1e8).astype(np.int64).reshape(K * nf, dim), srt], axis=1)
+        _, inv, counts = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+        inv = inv.ravel()
+        if np.any(counts > 2):
+            raise ValueError("more than two faces share a key")
+        self.etoe = np.tile(np.arange(K)[:, None], (1, nf))
+        self.etof = np.tile(np.arange(nf)[None, :], (K, 1))
+        srt_idx = np.argsort(inv, kind="stable")
+        grp = inv[srt_idx]
+        pair = np.nonzero(grp[1:] == grp[:-1])[0]
+        a, b = srt_idx[pair], srt_idx[pair + 1]
+        ea, fa, eb, fb = a // nf, a % nf, b // nf, b % nf
+        self.etoe[ea, fa], self.etof[ea, fa] = eb, fb
+        self.etoe[eb, fb], self.etof[eb, fb] = ea, fa
+        matched = np.zeros((K, nf), bool)
+        matched[ea, fa] = True
+        matched[eb, fb] = True
+        self.face_tag = np.zeros((K, nf), np.int8)
         if face_tag is not None:
             self.face_tag[:] = np.asarray(face_tag, np.int8)
-        unmatched = ~matched
-        if np.any(unmatched & (self.face_tag == INTERIOR)):
+        if np.any(~matched & (self.face_tag == INTERIOR)):
             raise ValueError("unmatched face without a boundary tag")
         self.face_tag[matched] = INTERIOR
         # node pairing on matched faces by coordinates modulo the period
         Np, Nfp = ref.Np, ref.Nfp
-        self.vmapP = np.zeros((self.K, nf, Nfp), np.int64)
-        for e in range(self.K):
-            for f in range(nf):
-                mine = self.nodes_x[e, ref.fmask[f]]                  # [Nfp, dim]
-                if not matched[e, f]:
-                    self.vmapP[e, f] = e * Np + ref.fmask[f]
-                    continue
-                e2, f2 = self.etoe[e, f], self.etof[e, f]
-                other = self.nodes_x[e2, ref.fmask[f2]]
-                d = _min_image(mine[:, None, :] - other[None, :, :], self.period)
-                dist = np.linalg.norm(d, axis=-1)
-                j = np.argmin(dist, axis=1)
-                if np.any(dist[np.arange(Nfp), j] > 1e-8 * scale):
-                    raise ValueError("face nodes do not match")
-                self.vmapP[e, f] = e2 * Np + ref.fmask[f2][j]
+        self.vmapP = (np.arange(K)[:, None, None] * Np + ref.fmask[None, :, :]).astype(np.int64)
+        ee, ff = np.nonzero(matched)
+        e2, f2 = self.etoe[ee, ff], self.etof[ee, ff]
+        mine = self.nodes_x[ee[:, None], ref.fmask[ff]]              # [M, Nfp, dim]
+        other = self.nodes_x[e2[:, None], ref.fmask[f2]]             # [M, Nfp, dim]
+        d = _min_image(mine[:, :, None, :] - other[:, None, :, :], self.period)
+        dist = np.linalg.norm(d, axis=-1)                            # [M, Nfp, Nfp]
+        j = np.argmin(dist, axis=2)
+        if np.any(np.take_along_axis(dist, j[..., None], axis=2) > 1e-8 * scale):
+            raise ValueError("face nodes do not match")
+        self.vmapP[ee, ff] = e2[:, None] * Np + ref.fmask[f2[:, None], j]
 
     def neighbours(self, elems: np.ndarray) -> np.ndarray:
         """Elements sharing a face with any element of ``elems`` (inclusive)."""

@@ -66,20 +66,20 @@ def kuhn_cube(n: int, lo: float = -math.pi, hi: float = math.pi):
     g = np.linspace(lo, hi, n + 1)
     Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
     vx = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
-    vid = lambda i, j, k: (k * (n + 1) + j) * (n + 1) + i
-    unit = np.eye(3, dtype=int)
-    tets = []
-    for k in range(n):
-        for j in range(n):
-            for i in range(n):
-                for perm in itertools.permutations(range(3)):
-                    p = np.array([i, j, k])
-                    vs = [vid(*p)]
-                    for ax in perm:
-                        p = p + unit[ax]
-                        vs.append(vid(*p))
-                    tets.append(vs)
-    etov = _orient(vx, np.array(tets, np.int64)).astype(np.int32)
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    base = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)          # cube corners, x fastest
+    vid = lambda p: (p[:, 2] * (n + 1) + p[:, 1]) * (n + 1) + p[:, 0]
+    unit = np.eye(3, dtype=np.int64)
+    per_cube = []
+    for perm in itertools.permutations(range(3)):
+        p = base.copy()
+        vs = [vid(p)]
+        for ax in perm:
+            p = p + unit[ax]
+            vs.append(vid(p))
+        per_cube.append(np.stack(vs, axis=1))
+    tets = np.stack(per_cube, axis=1).reshape(-1, 4)                     # cube-major order
+    etov = _orient(vx, tets.astype(np.int64)).astype(np.int32)
     L = hi - lo
     return vx, etov, np.array([L, L, L]), None
 
