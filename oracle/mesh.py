@@ -110,16 +110,18 @@ class Mesh:
         # node pairing on matched faces by coordinates modulo the period
         Np, Nfp = ref.Np, ref.Nfp
         self.vmapP = (np.arange(K)[:, None, None] * Np + ref.fmask[None, :, :]).astype(np.int64)
-        ee, ff = np.nonzero(matched)
-        e2, f2 = self.etoe[ee, ff], self.etof[ee, ff]
-        mine = self.nodes_x[ee[:, None], ref.fmask[ff]]              # [M, Nfp, dim]
-        other = self.nodes_x[e2[:, None], ref.fmask[f2]]             # [M, Nfp, dim]
-        d = _min_image(mine[:, :, None, :] - other[:, None, :, :], self.period)
-        dist = np.linalg.norm(d, axis=-1)                            # [M, Nfp, Nfp]
-        j = np.argmin(dist, axis=2)
-        if np.any(np.take_along_axis(dist, j[..., None], axis=2) > 1e-8 * scale):
-            raise ValueError("face nodes do not match")
-        self.vmapP[ee, ff] = e2[:, None] * Np + ref.fmask[f2[:, None], j]
+        ee_all, ff_all = np.nonzero(matched)
+        for c0 in range(0, ee_all.size, 65536):
+            ee, ff = ee_all[c0:c0 + 65536], ff_all[c0:c0 + 65536]
+            e2, f2 = self.etoe[ee, ff], self.etof[ee, ff]
+            mine = self.nodes_x[ee[:, None], ref.fmask[ff]]              # [M, Nfp, dim]
+            other = self.nodes_x[e2[:, None], ref.fmask[f2]]             # [M, Nfp, dim]
+            d = _min_image(mine[:, :, None, :] - other[:, None, :, :], self.period)
+            dist = np.linalg.norm(d, axis=-1)                            # [M, Nfp, Nfp]
+            j = np.argmin(dist, axis=2)
+            if np.any(np.take_along_axis(dist, j[..., None], axis=2) > 1e-8 * scale):
+                raise ValueError("face nodes do not match")
+            self.vmapP[ee, ff] = e2[:, None] * Np + ref.fmask[f2[:, None], j]
 
     def neighbours(self, elems: np.ndarray) -> np.ndarray:
         """Elements sharing a face with any element of ``elems`` (inclusive)."""

@@ -75,6 +75,35 @@ class Solver:
         self.t += dt
         self.step_index += 1
 
+    def step_patch(self, dt: float, elems) -> tuple:
+        """One SARK-4 step from the current state, evaluated only on the
+        domains of dependence of ``elems`` (each stage reaches one ring of face
+        neighbours further): F_0 on the 3-ring, F_1 on the 2-ring, F_2 on the
+        1-ring, F_3 on ``elems``.  Returns (sorted elems, q_{n+1} there).  The
+        solver state is not changed."""
+        mesh = self.mesh
+        rings = [np.unique(np.asarray(elems, np.int64))]
+        for _ in range(3):
+            rings.append(mesh.neighbours(rings[-1]))
+        R0, R1, R2, R3 = rings
+        cf = self.coefficients(dt)
+        xs, ws, _ = stage_positions(self.motion, self.X, self.x, self.t, dt)
+        qn = self.q
+        E = lambda i: cf.E[i][None, :, None]
+        a = {k: v[None, :, None] for k, v in cf.a.items()}
+        b = [cf.b[j][None, :, None] for j in range(4)]
+        F0, F1, F2 = (np.zeros_like(qn) for _ in range(3))
+        q1, q2, q3 = (np.zeros_like(qn) for _ in range(3))
+        F0[R3] = rhs(mesh, self.prm, qn, xs[0], ws[0], R3)
+        q1[R3] = E(1) * qn[R3] + dt * a[(1, 0)] * F0[R3]
+        F1[R2] = rhs(mesh, self.prm, q1, xs[1], ws[1], R2)
+        q2[R2] = E(2) * qn[R2] + dt * (a[(2, 0)] * F0[R2] + a[(2, 1)] * F1[R2])
+        F2[R1] = rhs(mesh, self.prm, q2, xs[2], ws[2], R1)
+        q3[R1] = E(3) * qn[R1] + dt * (a[(3, 0)] * F0[R1] + a[(3, 1)] * F1[R1] + a[(3, 2)] * F2[R1])
+        F3 = rhs(mesh, self.prm, q3, xs[3], ws[3], R0)
+        out = E(4) * qn[R0] + dt * (b[0] * F0[R0] + b[1] * F1[R0] + b[2] * F2[R0] + b[3] * F3)
+        return R0, out
+
     def run(self, dt: float, nsteps: int):
         for _ in range(nsteps):
             self.step(dt)

@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/gb.h"
-#include "gb_stage.hpp"
+#include "gb_stage_mfma.hpp"
 #include "host_ref.hpp"
 
 namespace {
@@ -190,10 +190,11 @@ hipError_t launch_stage(gb_solver *s, int kind, double dt, hipStream_t st) {
     (void)dt;
     gbd::KArgs<T> a{};
     a.K = m->K;
-    a.epb = s->epb;
-    a.nbatch = int((m->K + s->epb - 1) / s->epb);
+    a.epb = 16;
+    a.nbatch = int((m->K + 15) / 16);          // groups of 16 elements (one per wavefront)
     a.Nc = s->ref.Nc;
-    int grid = std::min(s->grid, a.nbatch);
+    // each workgroup (4 wavefronts) takes a contiguous range of groups
+    int grid = std::min(s->grid, (a.nbatch + 3) / 4);
     if (grid >= 8) grid = grid / 8 * 8;
     a.chunk = (a.nbatch + grid - 1) / grid;
     grid = (a.nbatch + a.chunk - 1) / a.chunk;
@@ -216,31 +217,29 @@ hipError_t launch_stage(gb_solver *s, int kind, double dt, hipStream_t st) {
     a.clock = s->clock.as<double>();
     a.kc = s->kconst.as<gbd::KConst<T>>();
     a.err = s->err.as<int>();
-    using S = gbd::Shape<DIM, N>;
-    const dim3 block(unsigned(s->epb * S::NP));
+    const dim3 block(256);
     const size_t lds = s->lds;
+    using K0 = decltype(&gbd::stage_mfma_kernel<DIM, N, T, 0>);
+    const K0 fns[5] = {&gbd::stage_mfma_kernel<DIM, N, T, 0>, &gbd::stage_mfma_kernel<DIM, N, T, 1>,
+                       &gbd::stage_mfma_kernel<DIM, N, T, 2>, &gbd::stage_mfma_kernel<DIM, N, T, 3>,
+                       &gbd::stage_mfma_kernel<DIM, N, T, 4>};
+    const K0 fn = fns[kind < 4 ? kind : 4];
     if (lds > 65536) {
-        const void *fns[5] = {(const void *)&gbd::stage_kernel<DIM, N, T, 0>, (const void *)&gbd::stage_kernel<DIM, N, T, 1>,
-                              (const void *)&gbd::stage_kernel<DIM, N, T, 2>, (const void *)&gbd::stage_kernel<DIM, N, T, 3>,
-                              (const void *)&gbd::stage_kernel<DIM, N, T, 4>};
-        hipError_t e = hipFuncSetAttribute(fns[kind < 4 ? kind : 4], hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
     }
-    switch (kind) {
-        case 0: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 0>), dim3(grid), block, lds, st, a); break;
-        case 1: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 1>), dim3(grid), block, lds, st, a); break;
-        case 2: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 2>), dim3(grid), block, lds, st, a); break;
-        case 3: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 3>), dim3(grid), block, lds, st, a); break;
-        default: hipLaunchKernelGGL((gbd::stage_kernel<DIM, N, T, 4>), dim3(grid), block, lds, st, a); break;
-    }
+    hipLaunchKernelGGL(fn, dim3(grid), block, lds, st, a);
     return hipGetLastError();
 }
 
 template <int DIM, int N, typename T>
-size_t lds_of(int Nc, int epb) { return gbd::lds_bytes<DIM, N, T>(Nc, epb); }
+size_t lds_of(int Nc, int epb) {
+    (void)epb;
+    return gbd::mfma_lds_bytes<DIM, N, T>((Nc + 15) / 16);
+}
 
 template <int DIM, int N>
-int ops_total_of(int Nc) { return gbd::OpOffsets<DIM, N>::total(Nc); }
+int ops_total_of(int Nc) { return gbd::MOps<DIM, N>::total((Nc + 15) / 16); }
 
 template <int DIM, int N, typename T>
 Launcher make_launcher() {
@@ -261,12 +260,20 @@ bool get_launcher(int dim, int N, int prec, Launcher &L) {
 
 // ---------------------------------------------------------------- conversion kernels
 
+// host layout [K][NF][NP] (FP64) <-> device blocked layout [K/16][NF][NP][16]
+__device__ __forceinline__ int64_t blocked_index(int64_t idx, int NP, int NF) {
+    const int64_t j = idx % NP;
+    const int64_t k = (idx / NP) % NF;
+    const int64_t e = idx / (int64_t(NP) * NF);
+    return (((e >> 4) * NF + k) * NP + j) * 16 + (e & 15);
+}
+
 template <typename T>
 __global__ void to_state_kernel(const double *in, T *out, int64_t n, int NP, int NF, double rho0) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= n) return;
     const int field = int((idx / NP) % NF);
-    out[idx] = T(field == 0 ? in[idx] - rho0 : in[idx]);
+    out[blocked_index(idx, NP, NF)] = T(field == 0 ? in[idx] - rho0 : in[idx]);
 }
 
 template <typename T>
@@ -274,25 +281,40 @@ __global__ void from_state_kernel(const T *in, double *out, int64_t n, int NP, i
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= n) return;
     const int field = int((idx / NP) % NF);
-    out[idx] = field == 0 ? double(in[idx]) + rho0 : double(in[idx]);
+    const double v = double(in[blocked_index(idx, NP, NF)]);
+    out[idx] = field == 0 ? v + rho0 : v;
 }
 
+// Operator fragments for the matrix-core stage kernel (layout of gbd::MOps).
 template <typename T>
-std::vector<T> pack_ops(const gbh::RefElement &R) {
+std::vector<T> pack_ops(const gbh::RefElement &R, std::vector<int32_t> &slot_table) {
     const int dim = R.dim, Np = R.Np, NFT = R.Nfaces * R.Nfp, Nc = R.Nc, nvert = dim + 1;
+    const int NJS = (Np + 3) / 4, NRT = (Np + 15) / 16, NMS = (NFT + 3) / 4, nct = (Nc + 15) / 16;
+    const bool f32 = sizeof(T) == 4;
+    auto crow = [&](int q, int r) { return f32 ? 4 * q + r : q + 4 * r; };
     std::vector<T> o;
-    o.reserve(size_t(dim) * Np * Np + size_t(NFT) * Np + 2 * size_t(Np) * Nc + Np * nvert);
+    auto frag = [&](auto val) {
+        for (int lane = 0; lane < 64; ++lane) o.push_back(T(val(lane & 15, lane >> 4)));
+    };
+    auto at = [](const gbh::Mat &M, int i, int j) { return (i < M.rows && j < M.cols) ? M(i, j) : 0.0; };
     for (int a = 0; a < dim; ++a)
-        for (int j = 0; j < Np; ++j)
-            for (int i = 0; i < Np; ++i) o.push_back(T(R.D[a](i, j)));
-    for (int m = 0; m < NFT; ++m)
-        for (int i = 0; i < Np; ++i) o.push_back(T(R.LIFT(i, m)));
-    for (int j = 0; j < Np; ++j)
-        for (int k = 0; k < Nc; ++k) o.push_back(T(R.Icub(k, j)));
-    for (int k = 0; k < Nc; ++k)
-        for (int i = 0; i < Np; ++i) o.push_back(T(R.Pcub(i, k)));
+        for (int rt = 0; rt < NRT; ++rt)
+            for (int st = 0; st < NJS; ++st)
+                frag([&](int c, int q) { return at(R.D[a], 16 * rt + c, 4 * st + q); });
+    for (int rt = 0; rt < NRT; ++rt)
+        for (int st = 0; st < NMS; ++st) frag([&](int c, int q) { return at(R.LIFT, 16 * rt + c, 4 * st + q); });
+    for (int t = 0; t < nct; ++t)
+        for (int st = 0; st < NJS; ++st) frag([&](int c, int q) { return at(R.Icub, 16 * t + c, 4 * st + q); });
+    for (int rt = 0; rt < NRT; ++rt)
+        for (int t = 0; t < nct; ++t)
+            for (int r = 0; r < 4; ++r) frag([&](int c, int q) { return at(R.Pcub, 16 * rt + c, 16 * t + crow(q, r)); });
     for (int i = 0; i < Np; ++i)
         for (int v = 0; v < nvert; ++v) o.push_back(T(R.bary(i, v)));
+    slot_table.assign(size_t(4 * NMS) * 2, -1);
+    for (int mm = 0; mm < NFT; ++mm) {
+        slot_table[2 * mm] = R.fmask[mm];
+        slot_table[2 * mm + 1] = mm / R.Nfp;
+    }
     return o;
 }
 
@@ -463,13 +485,23 @@ gb_status gb_mesh_create(gb_ctx *ctx, int dim, int N, int64_t nv, const double *
     GB_HIP(hipSetDevice(ctx->device));
     if (m->d_etov.alloc(size_t(K) * nvert * sizeof(int32_t)) != hipSuccess ||
         m->d_X.alloc(size_t(nv) * dim * sizeof(double)) != hipSuccess ||
-        m->d_x.alloc(size_t(nv) * dim * sizeof(double)) != hipSuccess ||
-        m->d_vmapP.alloc(m->conn.vmapP.size() * sizeof(int32_t)) != hipSuccess)
+        m->d_x.alloc(size_t(nv) * dim * sizeof(double)) != hipSuccess)
         return fail(GB_ERR_OOM, "device allocation for the mesh failed");
     GB_HIP(hipMemcpy(m->d_etov.p, etov, m->d_etov.bytes, hipMemcpyHostToDevice));
     GB_HIP(hipMemcpy(m->d_X.p, vx, m->d_X.bytes, hipMemcpyHostToDevice));
     GB_HIP(hipMemcpy(m->d_x.p, vx, m->d_x.bytes, hipMemcpyHostToDevice));
-    GB_HIP(hipMemcpy(m->d_vmapP.p, m->conn.vmapP.data(), m->d_vmapP.bytes, hipMemcpyHostToDevice));
+    {
+        // blocked trace map [K/16][slots][16] (slots = face nodes rounded up to
+        // a multiple of 4); -3 marks padding
+        const int NFT = m->ref.Nfaces * m->ref.Nfp;
+        const int slots = (NFT + 3) / 4 * 4;
+        const int64_t G = (K + 15) / 16;
+        std::vector<int32_t> blk(size_t(G) * slots * 16, -3);
+        for (int64_t e = 0; e < K; ++e)
+            for (int mm = 0; mm < NFT; ++mm) blk[((e >> 4) * slots + mm) * 16 + (e & 15)] = m->conn.vmapP[e * NFT + mm];
+        if (m->d_vmapP.alloc(blk.size() * sizeof(int32_t)) != hipSuccess) return fail(GB_ERR_OOM, "vmapP");
+        GB_HIP(hipMemcpy(m->d_vmapP.p, blk.data(), m->d_vmapP.bytes, hipMemcpyHostToDevice));
+    }
     m->motion.kind = 0;
     *out = m.release();
     return GB_OK;
@@ -528,7 +560,8 @@ gb_status gb_set_motion(gb_mesh *m, const gb_motion *mo) {
 gb_status gb_solver_footprint(const gb_mesh *m, const gb_params *p, size_t *bytes) {
     if (!m || !p || !bytes) return fail(GB_ERR_ARG, "NULL argument");
     const size_t es = p->precision == GB_FP32 ? 4 : 8;
-    *bytes = 4 * size_t(m->K) * n_fields(m->dim) * m->ref.Np * es;
+    *bytes = 4 * size_t((m->K + 15) / 16 * 16) * n_fields(m->dim) * m->ref.Np * es +
+             (5 + 4) * size_t(m->nv) * m->dim * sizeof(double);
     return GB_OK;
 }
 
@@ -551,18 +584,14 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     if (!get_launcher(m->dim, m->N, p->precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel for this configuration");
     s->elem_bytes = p->precision == GB_FP32 ? 4 : 8;
     const int Np = s->ref.Np;
-    // elements per workgroup: fill up to 256 threads within the LDS budget
-    const size_t budget = std::min<size_t>(m->ctx->max_lds, 65536);
-    int epb = std::max(1, 256 / Np);
-    while (epb > 1 && L.lds(s->ref.Nc, epb) > budget) --epb;
-    size_t need = L.lds(s->ref.Nc, epb);
+    const size_t need = L.lds(s->ref.Nc, 16);
     if (need > m->ctx->max_lds) return fail(GB_ERR_UNSUPPORTED, "reference operators exceed the LDS of one workgroup");
-    s->epb = epb;
+    s->epb = 16;
     s->lds = need;
     s->kconst_host.assign(std::max(sizeof(gbd::KConst<double>), sizeof(gbd::KConst<float>)), 0);
     s->grid = m->ctx->num_cu * 8;
     GB_HIP(hipSetDevice(m->ctx->device));
-    const size_t n = size_t(m->K) * s->NF * Np;
+    const size_t n = size_t((m->K + 15) / 16 * 16) * s->NF * Np;   // padded to whole groups of 16
     if (s->Q.alloc(n * s->elem_bytes) != hipSuccess || s->A.alloc(n * s->elem_bytes) != hipSuccess ||
         s->B.alloc(n * s->elem_bytes) != hipSuccess || s->G.alloc(n * s->elem_bytes) != hipSuccess ||
         s->clock.alloc(2 * sizeof(double)) != hipSuccess || s->err.alloc(sizeof(int)) != hipSuccess ||
@@ -570,18 +599,22 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
         s->vstage.alloc(5 * size_t(m->nv) * m->dim * sizeof(double)) != hipSuccess ||
         s->wstage.alloc(4 * size_t(m->nv) * m->dim * sizeof(double)) != hipSuccess)
         return fail(GB_ERR_OOM, "device allocation for the solver state failed");
+    std::vector<int32_t> slots;
     if (p->precision == GB_FP64) {
-        auto o = pack_ops<double>(s->ref);
+        auto o = pack_ops<double>(s->ref, slots);
+        if (int(o.size()) != L.ops_total(s->ref.Nc)) return fail(GB_ERR_ARG, "operator packing size mismatch");
         if (s->ops.alloc(o.size() * sizeof(double)) != hipSuccess) return fail(GB_ERR_OOM, "ops");
         GB_HIP(hipMemcpy(s->ops.p, o.data(), s->ops.bytes, hipMemcpyHostToDevice));
     } else {
-        auto o = pack_ops<float>(s->ref);
+        auto o = pack_ops<float>(s->ref, slots);
+        if (int(o.size()) != L.ops_total(s->ref.Nc)) return fail(GB_ERR_ARG, "operator packing size mismatch");
         if (s->ops.alloc(o.size() * sizeof(float)) != hipSuccess) return fail(GB_ERR_OOM, "ops");
         GB_HIP(hipMemcpy(s->ops.p, o.data(), s->ops.bytes, hipMemcpyHostToDevice));
     }
-    if (s->fmask.alloc(s->ref.fmask.size() * sizeof(int32_t)) != hipSuccess) return fail(GB_ERR_OOM, "fmask");
-    std::vector<int32_t> fm(s->ref.fmask.begin(), s->ref.fmask.end());
-    GB_HIP(hipMemcpy(s->fmask.p, fm.data(), s->fmask.bytes, hipMemcpyHostToDevice));
+    if (s->fmask.alloc(slots.size() * sizeof(int32_t)) != hipSuccess) return fail(GB_ERR_OOM, "slot table");
+    GB_HIP(hipMemcpy(s->fmask.p, slots.data(), s->fmask.bytes, hipMemcpyHostToDevice));
+    // padding elements of the last group stay zero
+    for (DevBuf *b : {&s->Q, &s->A, &s->B, &s->G}) GB_HIP(hipMemset(b->p, 0, b->bytes));
     GB_HIP(hipMemset(s->err.p, 0, sizeof(int)));
     double clk[2] = {0.0, 0.0};
     GB_HIP(hipMemcpy(s->clock.p, clk, sizeof(clk), hipMemcpyHostToDevice));
@@ -661,10 +694,12 @@ gb_status gb_rhs(gb_solver *s, const double *q, double *F) {
     GB_HIP(hipSetDevice(m->ctx->device));
     hipStream_t st = m->ctx->stream;
     const int64_t n = m->K * s->NF * s->ref.Np;
+    const int64_t npad = (m->K + 15) / 16 * 16 * s->NF * s->ref.Np;
     DevBuf dq, din, dout;
-    if (dq.alloc(size_t(n) * sizeof(double)) != hipSuccess || din.alloc(size_t(n) * s->elem_bytes) != hipSuccess ||
-        dout.alloc(size_t(n) * s->elem_bytes) != hipSuccess)
+    if (dq.alloc(size_t(n) * sizeof(double)) != hipSuccess || din.alloc(size_t(npad) * s->elem_bytes) != hipSuccess ||
+        dout.alloc(size_t(npad) * s->elem_bytes) != hipSuccess)
         return fail(GB_ERR_OOM, "rhs buffers");
+    GB_HIP(hipMemsetAsync(din.p, 0, din.bytes, st));
     GB_HIP(hipMemcpyAsync(dq.p, q, size_t(n) * sizeof(double), hipMemcpyHostToDevice, st));
     const unsigned nb = unsigned((n + 255) / 256);
     const double rho0 = s->prm.precision == GB_FP32 ? s->prm.rho0 : 0.0;

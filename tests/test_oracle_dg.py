@@ -344,3 +344,19 @@ def test_free_stream_paper_setup_magnitude():
     err = s.l2_norm(c * (s.q - q0))          # rho u = c q2
     bound = 10 * max(g["rho_u_error"])
     assert err[1] < bound and err[2] < bound
+
+
+def test_patch_step_equals_full_step():
+    """The domain-of-dependence step used for sampled parity at full size
+    reproduces the full step exactly on the sampled elements."""
+    cs = make_case("C1", n=6)
+    mot = dict(cs.motion)
+    kind = mot.pop("kind")
+    s = _solver(cs.vx, cs.etov, cs.period, 3, tau=cs.tau, motion=Motion(kind, **mot))
+    X = s.node_coords()
+    rho, u = cs.macroscopic(X)
+    s.set_state(gb.equilibrium(2, rho, u, 1.0).transpose(1, 0, 2))
+    s.run(cs.dt, 2)
+    elems, qp = s.step_patch(cs.dt, [3, 17, 40])
+    s.step(cs.dt)
+    assert np.abs(qp - s.q[elems]).max() == 0.0
