@@ -41,7 +41,7 @@ def algorithmic_bytes_per_launch(K: int, Np: int, NF: int, dim: int, elem_bytes:
     return state + geom
 
 
-def run_gpu(precision_name: str, steps: int, warmup: int, n: int):
+def run_gpu(precision_name: str, steps: int, warmup: int, n: int, graph: bool = True):
     import numpy as np
     import torch
 
@@ -67,15 +67,17 @@ def run_gpu(precision_name: str, steps: int, warmup: int, n: int):
     L.gb_solver_time_stages(s.solver, False)
     q, t, nstep = s.get_state()
     # graph replay of the same step, timed separately
-    s2 = Session(case, precision=prec, device=0, stream=stream)
-    s2.set_state(q0)
-    s2.step(case.dt, warmup, graph=True)
-    torch.cuda.synchronize()
-    g0 = time.perf_counter()
-    s2.step(case.dt, steps, graph=True)
-    torch.cuda.synchronize()
-    gel = time.perf_counter() - g0
-    s2.close()
+    gel = float("nan")
+    if graph:
+        s2 = Session(case, precision=prec, device=0, stream=stream)
+        s2.set_state(q0)
+        s2.step(case.dt, warmup, graph=True)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        s2.step(case.dt, steps, graph=True)
+        torch.cuda.synchronize()
+        gel = time.perf_counter() - g0
+        s2.close()
     K, Np, NF = s.K, s.Np, s.NF
     s.close()
     dof = K * Np * NF
@@ -129,6 +131,9 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="quads per side (256 = the configuration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 512 MiB buffer three times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -137,8 +142,16 @@ def main():
 
     import numpy as np
 
-    r32 = run_gpu("f32", args.steps, args.warmup, args.n)
-    r64 = None if args.no_fp64 else run_gpu("f64", args.steps, args.warmup, args.n)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    r32 = run_gpu("f32", args.steps, args.warmup, args.n, graph=not args.no_graph)
+    r64 = None if args.no_fp64 else run_gpu("f64", args.steps, args.warmup, args.n, graph=not args.no_graph)
 
     case = r32["case"]
     K, Np, NF = r32["K"], r32["Np"], r32["NF"]
@@ -168,7 +181,7 @@ def main():
                      "bytes_per_launch": bytes_launch, "avg_launch_ms": round(r32["stage_avg_ms"], 5),
                      "launches": r32["stage_launches"],
                      "avg_ms_by_stage": [round(x, 5) for x in r32["stage_ms_by_kind"]]},
-        "graph_replay_gdof_stage_s": round(r32["graph_gdof_stage_s"], 3),
+        "graph_replay_gdof_stage_s": (None if args.no_graph else round(r32["graph_gdof_stage_s"], 3)),
     }
     if r64 is not None:
         b64 = algorithmic_bytes_per_launch(K, Np, NF, 2, 8)
@@ -176,7 +189,7 @@ def main():
         u32 = r32["q"][:, 1:3] / r32["q"][:, 0:1]
         u64 = r64["q"][:, 1:3] / r64["q"][:, 0:1]
         out["fp64"] = {"gdof_stage_s": round(r64["gdof_stage_s"], 3),
-                       "graph_gdof_stage_s": round(r64["graph_gdof_stage_s"], 3),
+                       "graph_gdof_stage_s": (None if args.no_graph else round(r64["graph_gdof_stage_s"], 3)),
                        "ms_per_step": round(r64["seconds"] / args.steps * 1e3, 4),
                        "stage_avg_ms": round(r64["stage_avg_ms"], 5),
                        "achieved_GBs": round(a64, 1), "frac": round(a64 / HBM_PEAK_GBS, 4)}

@@ -132,7 +132,7 @@ __device__ __forceinline__ void sub_cMd(T c, const T *g, T *out) {
 // diagonal, m_a^2 / (sqrt2 tau rho) on it.
 template <int DIM, typename T>
 __device__ __forceinline__ void ntilde(T rho, const T *m, T inv_tau, T *out) {
-    const T k = inv_tau / rho;
+    const T k = inv_tau * (T(1) / rho);
     const T kd = k * T(1.0 / kSqrt2);
     if constexpr (DIM == 2) {
         out[0] = k * m[0] * m[1];

@@ -1,0 +1,104 @@
+// Host-side launch of the fused stage kernel for one element shape and
+// precision.  Each (dimension, order, precision) is compiled in a translation
+// unit of its own (gb_shape_*.hip) so the kernels build in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gb_stage_mfma.hpp"
+
+namespace gbd {
+
+// Everything a stage launch needs from the solver.
+struct LaunchArgs {
+    int64_t K = 0;
+    int64_t nv = 0;
+    int Nc = 0;
+    int grid = 1;              // workgroups for a full chip (CUs x 8)
+    size_t lds = 0;            // dynamic LDS bytes per workgroup
+    const int32_t *etov = nullptr;
+    const double *vstage = nullptr;   // [5][nv][dim] stage vertex positions
+    const double *wstage = nullptr;   // [4][nv][dim] stage vertex velocities
+    const int32_t *vmapP = nullptr;
+    const void *ops = nullptr;
+    const int32_t *fmask = nullptr;
+    void *Q = nullptr, *A = nullptr, *B = nullptr, *G = nullptr;
+    const double *clock = nullptr;
+    const void *kc = nullptr;
+    int *err = nullptr;
+};
+
+struct ShapeEntry {
+    hipError_t (*stage)(const LaunchArgs &, int kind, hipStream_t);
+    size_t (*lds)(int Nc);
+    int (*ops_total)(int Nc);
+};
+
+// Stage kinds 0..3 are the SARK-4 stages, 4 the plain right-hand side.
+template <int DIM, int N, typename T>
+hipError_t launch_stage(const LaunchArgs &L, int kind, hipStream_t st) {
+    KArgs<T> a{};
+    a.K = L.K;
+    a.epb = 16;
+    a.nbatch = int((L.K + 15) / 16);          // groups of 16 elements (one per wavefront)
+    a.Nc = L.Nc;
+    // each workgroup (kWaves wavefronts) takes a contiguous range of groups
+    int grid = std::min(L.grid, (a.nbatch + kWaves - 1) / kWaves);
+    if (grid >= 8) grid = grid / 8 * 8;
+    a.chunk = (a.nbatch + grid - 1) / grid;
+    grid = (a.nbatch + a.chunk - 1) / a.chunk;
+    // the XCD-major remap needs a multiple of 8; surplus workgroups find no group
+    if (grid >= 8 && grid % 8) grid = (grid + 7) / 8 * 8;
+    a.etov = L.etov;
+    {
+        const int64_t stride = L.nv * DIM;
+        const int slot = kind == 4 ? 0 : kind;
+        a.xs = L.vstage + slot * stride;
+        a.ws = L.wstage + slot * stride;
+    }
+    a.vmapP = L.vmapP;
+    a.ops = static_cast<const T *>(L.ops);
+    a.fmask = L.fmask;
+    a.Q = static_cast<T *>(L.Q);
+    a.A = static_cast<T *>(L.A);
+    a.B = static_cast<T *>(L.B);
+    a.G = static_cast<T *>(L.G);
+    a.clock = L.clock;
+    a.kc = static_cast<const KConst<T> *>(L.kc);
+    a.err = L.err;
+    const dim3 block(64 * kWaves);
+    using K0 = decltype(&stage_mfma_kernel<DIM, N, T, 0>);
+    const K0 fns[5] = {&stage_mfma_kernel<DIM, N, T, 0>, &stage_mfma_kernel<DIM, N, T, 1>,
+                       &stage_mfma_kernel<DIM, N, T, 2>, &stage_mfma_kernel<DIM, N, T, 3>,
+                       &stage_mfma_kernel<DIM, N, T, 4>};
+    const K0 fn = fns[kind < 4 ? kind : 4];
+    if (L.lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), block, L.lds, st, a);
+    return hipGetLastError();
+}
+
+template <int DIM, int N, typename T>
+size_t stage_lds(int Nc) { return mfma_lds_bytes<DIM, N, T>((Nc + 15) / 16); }
+
+template <int DIM, int N>
+int stage_ops_total(int Nc) { return MOps<DIM, N>::total((Nc + 15) / 16); }
+
+template <int DIM, int N, typename T>
+ShapeEntry shape_entry() { return ShapeEntry{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N>}; }
+
+}  // namespace gbd
+
+#define GB_SHAPE_NAME(D, NN, P) shape_##D##_##NN##_##P
+#define GB_DECLARE_SHAPE(D, NN, P) namespace gbd { ShapeEntry GB_SHAPE_NAME(D, NN, P)(); }
+#define GB_DEFINE_SHAPE(D, NN, P, TYPE) \
+    namespace gbd { ShapeEntry GB_SHAPE_NAME(D, NN, P)() { return shape_entry<D, NN, TYPE>(); } }
+
+#define GB_ALL_SHAPES(X) \
+    X(2, 1, f32) X(2, 1, f64) X(2, 2, f32) X(2, 2, f64) X(2, 3, f32) X(2, 3, f64) \
+    X(2, 4, f32) X(2, 4, f64) X(2, 5, f32) X(2, 5, f64) \
+    X(3, 1, f32) X(3, 1, f64) X(3, 2, f32) X(3, 2, f64) X(3, 3, f32) X(3, 3, f64)

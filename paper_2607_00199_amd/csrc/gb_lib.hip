@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/gb.h"
-#include "gb_stage_mfma.hpp"
+#include "gb_launch.hpp"
 #include "host_ref.hpp"
 
 namespace {
@@ -107,11 +107,12 @@ namespace {
 // ---------------------------------------------------------------- dispatch
 
 struct Launcher {
-    // launches one stage kind; returns hipError_t
-    hipError_t (*stage)(gb_solver *s, int kind, double dt, hipStream_t st);
-    hipError_t (*prepare)(gb_solver *s, double dt, hipStream_t st);
-    size_t (*lds)(int Nc, int epb);
-    int (*ops_total)(int Nc);
+    gbd::ShapeEntry shape{};
+    hipError_t (*prepare)(gb_solver *s, double dt, hipStream_t st) = nullptr;
+    // launches one stage kind (0..3 SARK-4 stages, 4 right-hand side only)
+    hipError_t stage(gb_solver *s, int kind, double dt, hipStream_t st) const;
+    size_t lds(int Nc) const { return shape.lds(Nc); }
+    int ops_total(int Nc) const { return shape.ops_total(Nc); }
 };
 
 template <typename T>
@@ -156,6 +157,16 @@ void fill_kconst(gbd::KConst<T> &k, const gb_solver *s, double dt) {
     double fv[25];
     flux_vinv(fv);
     for (int p = 0; p < 25; ++p) k.fluxV[p] = T(fv[p]);
+    {
+        // (c M_n)^- = sum_p fluxA[p] M_n^p: interpolate min(c lambda, 0) on the spectrum
+        const double c = s->prm.c, s3 = std::sqrt(3.0);
+        const double g[5] = {-c * s3, -c, 0.0, 0.0, 0.0};
+        for (int p = 0; p < 5; ++p) {
+            double acc = 0.0;
+            for (int l = 0; l < 5; ++l) acc += fv[p * 5 + l] * g[l];
+            k.fluxA[p] = T(acc);
+        }
+    }
     for (int f = 0; f < 10; ++f) k.q_inf[f] = T(s->prm.q_inf[f] - (f == 0 ? rho0 : 0.0));
     k.sponge = s->prm.sponge_sigma_max > 0.0;
     k.sp_cx = s->prm.sponge_cx;
@@ -184,78 +195,48 @@ hipError_t prepare_consts(gb_solver *s, double dt, hipStream_t st) {
     return hipSuccess;
 }
 
-template <int DIM, int N, typename T>
-hipError_t launch_stage(gb_solver *s, int kind, double dt, hipStream_t st) {
-    gb_mesh *m = s->mesh;
-    (void)dt;
-    gbd::KArgs<T> a{};
-    a.K = m->K;
-    a.epb = 16;
-    a.nbatch = int((m->K + 15) / 16);          // groups of 16 elements (one per wavefront)
-    a.Nc = s->ref.Nc;
-    // each workgroup (4 wavefronts) takes a contiguous range of groups
-    int grid = std::min(s->grid, (a.nbatch + 3) / 4);
-    if (grid >= 8) grid = grid / 8 * 8;
-    a.chunk = (a.nbatch + grid - 1) / grid;
-    grid = (a.nbatch + a.chunk - 1) / a.chunk;
-    // the XCD-major remap needs a multiple of 8; surplus workgroups find no batch
-    if (grid >= 8 && grid % 8) grid = (grid + 7) / 8 * 8;
-    a.etov = m->d_etov.as<int32_t>();
-    {
-        const int64_t st = m->nv * DIM;
-        const int slot = kind == 4 ? 0 : kind;
-        a.xs = s->vstage.as<double>() + slot * st;
-        a.ws = s->wstage.as<double>() + slot * st;
-    }
-    a.vmapP = m->d_vmapP.as<int32_t>();
-    a.ops = s->ops.as<T>();
-    a.fmask = s->fmask.as<int32_t>();
-    a.Q = s->Q.as<T>();
-    a.A = s->A.as<T>();
-    a.B = s->B.as<T>();
-    a.G = s->G.as<T>();
-    a.clock = s->clock.as<double>();
-    a.kc = s->kconst.as<gbd::KConst<T>>();
-    a.err = s->err.as<int>();
-    const dim3 block(256);
-    const size_t lds = s->lds;
-    using K0 = decltype(&gbd::stage_mfma_kernel<DIM, N, T, 0>);
-    const K0 fns[5] = {&gbd::stage_mfma_kernel<DIM, N, T, 0>, &gbd::stage_mfma_kernel<DIM, N, T, 1>,
-                       &gbd::stage_mfma_kernel<DIM, N, T, 2>, &gbd::stage_mfma_kernel<DIM, N, T, 3>,
-                       &gbd::stage_mfma_kernel<DIM, N, T, 4>};
-    const K0 fn = fns[kind < 4 ? kind : 4];
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(fn, dim3(grid), block, lds, st, a);
-    return hipGetLastError();
-}
-
-template <int DIM, int N, typename T>
-size_t lds_of(int Nc, int epb) {
-    (void)epb;
-    return gbd::mfma_lds_bytes<DIM, N, T>((Nc + 15) / 16);
-}
-
-template <int DIM, int N>
-int ops_total_of(int Nc) { return gbd::MOps<DIM, N>::total((Nc + 15) / 16); }
-
-template <int DIM, int N, typename T>
-Launcher make_launcher() {
-    return Launcher{&launch_stage<DIM, N, T>, &prepare_consts<T>, &lds_of<DIM, N, T>, &ops_total_of<DIM, N>};
-}
+#define GB_DECL(D, NN, P) GB_DECLARE_SHAPE(D, NN, P)
+}  // namespace
+GB_ALL_SHAPES(GB_DECL)
+namespace {
+#undef GB_DECL
 
 bool get_launcher(int dim, int N, int prec, Launcher &L) {
-#define GB_CASE(D, NN)                                                                              \
-    if (dim == D && N == NN) {                                                                      \
-        L = prec == GB_FP64 ? make_launcher<D, NN, double>() : make_launcher<D, NN, float>();      \
-        return true;                                                                                \
+    const bool f64 = prec == GB_FP64;
+#define GB_CASE(D, NN, P)                                                  \
+    if (dim == D && N == NN && f64 == (#P[1] == '6')) {                  \
+        L.shape = gbd::GB_SHAPE_NAME(D, NN, P)();                          \
+        L.prepare = f64 ? &prepare_consts<double> : &prepare_consts<float>; \
+        return true;                                                       \
     }
-    GB_CASE(2, 1) GB_CASE(2, 2) GB_CASE(2, 3) GB_CASE(2, 4) GB_CASE(2, 5)
-    GB_CASE(3, 1) GB_CASE(3, 2) GB_CASE(3, 3)
+    GB_ALL_SHAPES(GB_CASE)
 #undef GB_CASE
     return false;
+}
+
+hipError_t Launcher::stage(gb_solver *s, int kind, double dt, hipStream_t st) const {
+    (void)dt;
+    const gb_mesh *m = s->mesh;
+    gbd::LaunchArgs a;
+    a.K = m->K;
+    a.nv = m->nv;
+    a.Nc = s->ref.Nc;
+    a.grid = s->grid;
+    a.lds = s->lds;
+    a.etov = m->d_etov.as<int32_t>();
+    a.vstage = s->vstage.as<double>();
+    a.wstage = s->wstage.as<double>();
+    a.vmapP = m->d_vmapP.as<int32_t>();
+    a.ops = s->ops.p;
+    a.fmask = s->fmask.as<int32_t>();
+    a.Q = s->Q.p;
+    a.A = s->A.p;
+    a.B = s->B.p;
+    a.G = s->G.p;
+    a.clock = s->clock.as<double>();
+    a.kc = s->kconst.p;
+    a.err = s->err.as<int>();
+    return shape.stage(a, kind, st);
 }
 
 // ---------------------------------------------------------------- conversion kernels
@@ -584,7 +565,7 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     if (!get_launcher(m->dim, m->N, p->precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel for this configuration");
     s->elem_bytes = p->precision == GB_FP32 ? 4 : 8;
     const int Np = s->ref.Np;
-    const size_t need = L.lds(s->ref.Nc, 16);
+    const size_t need = L.lds(s->ref.Nc);
     if (need > m->ctx->max_lds) return fail(GB_ERR_UNSUPPORTED, "reference operators exceed the LDS of one workgroup");
     s->epb = 16;
     s->lds = need;

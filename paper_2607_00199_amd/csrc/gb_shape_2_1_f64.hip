@@ -1,0 +1,3 @@
+// Stage kernels of the 2D order-1 element in FP64.
+#include "gb_launch.hpp"
+GB_DEFINE_SHAPE(2, 1, f64, double)

@@ -1,0 +1,3 @@
+// Stage kernels of the 2D order-2 element in FP32.
+#include "gb_launch.hpp"
+GB_DEFINE_SHAPE(2, 2, f32, float)

@@ -1,0 +1,3 @@
+// Stage kernels of the 3D order-1 element in FP32.
+#include "gb_launch.hpp"
+GB_DEFINE_SHAPE(3, 1, f32, float)

@@ -1,0 +1,3 @@
+// Stage kernels of the 3D order-2 element in FP64.
+#include "gb_launch.hpp"
+GB_DEFINE_SHAPE(3, 2, f64, double)

@@ -41,6 +41,7 @@ struct KConst {
     T c, inv_tau, rho0;
     int flux_mode;       // 0 split, 1 relative
     T fluxV[25];         // row p: coefficients of g -> power p of M_n
+    T fluxA[5];          // split mode: coefficients of (c M_n)^- as a polynomial in M_n
     T q_inf[10];
     int sponge;
     double sp_cx, sp_cy, sp_r0, sp_r1, sp_smax;

@@ -118,11 +118,30 @@ struct MOps {
     __host__ __device__ static constexpr int slots() { return 4 * M::NMS; }
 };
 
+// Workgroup LDS: operator fragments, the slot table, then one stage-input
+// block [NF][Np][16] per wavefront (kWaves wavefronts of 64 lanes).
+constexpr int kWaves = 4;
+
 template <int DIM, int N, typename T>
-inline size_t mfma_lds_bytes(int nct) {
+__host__ __device__ inline size_t mfma_lds_state_offset(int nct) {
     size_t b = size_t(MOps<DIM, N>::total(nct)) * sizeof(T);
     b = (b + 15) / 16 * 16;
-    return b + size_t(MOps<DIM, N>::slots()) * 2 * sizeof(int32_t);
+    b += size_t(MOps<DIM, N>::slots()) * 2 * sizeof(int32_t);
+    return (b + 15) / 16 * 16;
+}
+
+// The stage-input block is staged in LDS unless the operators already take
+// most of it (tetrahedra of order 3 in FP64: about 80 KB of fragments).
+template <int DIM, int N, typename T>
+__host__ __device__ constexpr bool stage_in_lds() {
+    return !(DIM == 3 && N >= 3 && sizeof(T) == 8);
+}
+
+template <int DIM, int N, typename T>
+inline size_t mfma_lds_bytes(int nct) {
+    using S = Shape<DIM, N>;
+    const size_t state = stage_in_lds<DIM, N, T>() ? size_t(kWaves) * S::NF * S::NP * 16 * sizeof(T) : 0;
+    return mfma_lds_state_offset<DIM, N, T>(nct) + state;
 }
 
 // Blocked state address of (element e, field k, node j).
@@ -149,8 +168,17 @@ __device__ __forceinline__ T stage_in_at(const T *Q, const T *A, const T *B, con
     }
 }
 
+// Occupancy target: two wavefronts per SIMD for the FP32 triangle kernels
+// with one 16-row node tile (their registers fit that budget without
+// spills); the others need the whole register file.
+template <int DIM, int N>
+__host__ __device__ constexpr int stage_waves_per_eu(int elem_bytes) {
+    return (elem_bytes == 4 && DIM == 2 && MShape<DIM, N>::NRT == 1) ? 2 : 1;
+}
+
 template <int DIM, int N, typename T, int STAGE>
-__global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<DIM, N>(sizeof(T)))))
+stage_mfma_kernel(KArgs<T> a) {
     using S = Shape<DIM, N>;
     using MS = MShape<DIM, N>;
     using O = MOps<DIM, N>;
@@ -175,6 +203,8 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
     const int col = lane & 15;
     const int q4 = lane >> 4;
     const T *BARY = s_ops + O::bary(nct);
+    constexpr int BLK = NF * NP * 16;
+    T *s_q = reinterpret_cast<T *>(smem + mfma_lds_state_offset<DIM, N, T>(nct)) + wave * BLK;
 
     int logical = blockIdx.x;
     if ((gridDim.x & 7) == 0) logical = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
@@ -192,8 +222,49 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
         const int64_t gbase = int64_t(g) * GSTRIDE;
         const T *Qg = a.Q + gbase, *Ag = a.A + gbase, *Bg = a.B + gbase;
         T *Qw = a.Q + gbase, *Aw = a.A + gbase, *Bw = a.B + gbase, *Gw = a.G + gbase;
+
+        // ---- loads, issued together so that a group costs the wave about
+        //      three memory round trips rather than one per operand: trace
+        //      map and vertex ids; the group's stage input (one contiguous
+        //      block) copied to this wave's LDS; the first face slot's
+        //      neighbour values and the stage vertex data
+        const int32_t *vmg = a.vmapP + int64_t(g) * (O::slots() * 16) + q4 * 16 + col;
+        int32_t vm_cur = vmg[0];
+        int32_t vm_nxt = NMS > 1 ? vmg[64] : 0;
+        int32_t vid[NVERT];
+#pragma unroll
+        for (int v = 0; v < NVERT; ++v) vid[v] = valid ? a.etov[e * NVERT + v] : 0;
+        constexpr bool LDS_IN = stage_in_lds<DIM, N, T>();
+        if constexpr (LDS_IN) {
+#pragma unroll
+            for (int k = 0; k < NF; ++k)
+#pragma unroll
+                for (int p = lane; p < NP * 16; p += 64)
+                    s_q[k * NP * 16 + p] = stage_in_at<NCONS, STAGE, T>(Qg, Ag, Bg, kc, k, k * NP * 16 + p);
+        }
+        // neighbour values of face slot s2 (boundary and padding slots read
+        // this lane's own, always allocated, node: every load is in bounds)
+        auto gather = [&](int s2, int32_t idx, T *out) {
+            const int vm = s_slot[2 * (4 * s2 + q4)];
+            int64_t off = gbase + (vm > 0 ? vm : 0) * 16 + col;
+            if (idx >= 0) {
+                const int e2 = idx / NP;
+                const int j2 = idx - e2 * NP;
+                off = (int64_t(e2 >> 4) * (NF * NP) + j2) * 16 + (e2 & 15);
+            }
+#pragma unroll
+            for (int k = 0; k < NF; ++k) out[k] = stage_in_at<NCONS, STAGE, T>(a.Q, a.A, a.B, kc, k, off + k * NP * 16);
+        };
+        T nb_cur[NF];
+        gather(0, vm_cur, nb_cur);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         auto own = [&](int k, int j) -> T {
-            return stage_in_at<NCONS, STAGE, T>(Qg, Ag, Bg, kc, k, (k * NP + j) * 16 + col);
+            if constexpr (LDS_IN)
+                return s_q[(k * NP + j) * 16 + col];
+            else
+                return stage_in_at<NCONS, STAGE, T>(Qg, Ag, Bg, kc, k, (k * NP + j) * 16 + col);
         };
 
         // ---- geometry of this lane's element (FP64; the four lanes of an
@@ -202,7 +273,7 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
         {
             double xv[NVERT][DIM], wv[NVERT][DIM];
             for (int v = 0; v < NVERT; ++v) {
-                const int64_t gv = valid ? int64_t(a.etov[e * NVERT + v]) : 0;
+                const int64_t gv = vid[v];
                 for (int d = 0; d < DIM; ++d) {
                     xv[v][d] = valid ? a.xs[gv * DIM + d] : (v == d + 1 ? 1.0 : 0.0);
                     wv[v][d] = valid ? a.ws[gv * DIM + d] : 0.0;
@@ -214,39 +285,43 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
             double J, inv[DIM][DIM];
             if constexpr (DIM == 2) {
                 J = Gm[0][0] * Gm[1][1] - Gm[0][1] * Gm[1][0];
-                inv[0][0] = Gm[1][1] / J;
-                inv[0][1] = -Gm[0][1] / J;
-                inv[1][0] = -Gm[1][0] / J;
-                inv[1][1] = Gm[0][0] / J;
+                const double iJ = 1.0 / J;
+                inv[0][0] = Gm[1][1] * iJ;
+                inv[0][1] = -Gm[0][1] * iJ;
+                inv[1][0] = -Gm[1][0] * iJ;
+                inv[1][1] = Gm[0][0] * iJ;
             } else {
                 const double c00 = Gm[1][1] * Gm[2][2] - Gm[1][2] * Gm[2][1];
                 const double c01 = Gm[1][2] * Gm[2][0] - Gm[1][0] * Gm[2][2];
                 const double c02 = Gm[1][0] * Gm[2][1] - Gm[1][1] * Gm[2][0];
                 J = Gm[0][0] * c00 + Gm[0][1] * c01 + Gm[0][2] * c02;
-                inv[0][0] = c00 / J;
-                inv[1][0] = c01 / J;
-                inv[2][0] = c02 / J;
-                inv[0][1] = (Gm[0][2] * Gm[2][1] - Gm[0][1] * Gm[2][2]) / J;
-                inv[1][1] = (Gm[0][0] * Gm[2][2] - Gm[0][2] * Gm[2][0]) / J;
-                inv[2][1] = (Gm[0][1] * Gm[2][0] - Gm[0][0] * Gm[2][1]) / J;
-                inv[0][2] = (Gm[0][1] * Gm[1][2] - Gm[0][2] * Gm[1][1]) / J;
-                inv[1][2] = (Gm[0][2] * Gm[1][0] - Gm[0][0] * Gm[1][2]) / J;
-                inv[2][2] = (Gm[0][0] * Gm[1][1] - Gm[0][1] * Gm[1][0]) / J;
+                const double iJ = 1.0 / J;
+                inv[0][0] = c00 * iJ;
+                inv[1][0] = c01 * iJ;
+                inv[2][0] = c02 * iJ;
+                inv[0][1] = (Gm[0][2] * Gm[2][1] - Gm[0][1] * Gm[2][2]) * iJ;
+                inv[1][1] = (Gm[0][0] * Gm[2][2] - Gm[0][2] * Gm[2][0]) * iJ;
+                inv[2][1] = (Gm[0][1] * Gm[2][0] - Gm[0][0] * Gm[2][1]) * iJ;
+                inv[0][2] = (Gm[0][1] * Gm[1][2] - Gm[0][2] * Gm[1][1]) * iJ;
+                inv[1][2] = (Gm[0][2] * Gm[1][0] - Gm[0][0] * Gm[1][2]) * iJ;
+                inv[2][2] = (Gm[0][0] * Gm[1][1] - Gm[0][1] * Gm[1][0]) * iJ;
             }
             if (valid && q4 == 0 && !(J > 0.0)) atomicOr(a.err, 1);
 #pragma unroll
             for (int aa = 0; aa < DIM; ++aa)
 #pragma unroll
                 for (int ii = 0; ii < DIM; ++ii) met[aa * DIM + ii] = T(inv[aa][ii]);
+            const double halfiJ = 0.5 / J;
             if constexpr (DIM == 2) {
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
                     const int va = f, vb = (f + 1) % 3;
                     const double tx = xv[vb][0] - xv[va][0], ty = xv[vb][1] - xv[va][1];
                     const double len = sqrt(tx * tx + ty * ty);
-                    nrm[2 * f] = T(ty / len);
-                    nrm[2 * f + 1] = T(-tx / len);
-                    fsc[f] = T(0.5 * len / J);
+                    const double il = 1.0 / len;
+                    nrm[2 * f] = T(ty * il);
+                    nrm[2 * f + 1] = T(-tx * il);
+                    fsc[f] = T(len * halfiJ);
                 }
             } else {
                 const int fv[4][4] = {{0, 1, 2, 3}, {0, 1, 3, 2}, {1, 2, 3, 0}, {0, 2, 3, 1}};
@@ -262,10 +337,11 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
                         n2 = -n2;
                     }
                     const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-                    nrm[3 * f] = T(n0 / nn);
-                    nrm[3 * f + 1] = T(n1 / nn);
-                    nrm[3 * f + 2] = T(n2 / nn);
-                    fsc[f] = T(0.25 * nn / J);
+                    const double inn = 1.0 / nn;
+                    nrm[3 * f] = T(n0 * inn);
+                    nrm[3 * f + 1] = T(n1 * inn);
+                    nrm[3 * f + 2] = T(n2 * inn);
+                    fsc[f] = T(0.5 * nn * halfiJ);   // sJ / J with sJ = area / 2 = |n| / 4
                 }
             }
 #pragma unroll
@@ -365,25 +441,30 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
                 }
         }
 
-        // ---- surface term: upwind flux at this lane's face slots, lifted by MFMA
+        // ---- surface term: upwind flux at this lane's face slots, lifted by
+        //      MFMA; the next slot's neighbour values are in flight meanwhile
 #pragma unroll 1
         for (int s2 = 0; s2 < NMS; ++s2) {
             const int m = 4 * s2 + q4;
+            const int32_t idx = vm_cur;
+            T nbv[NF];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) nbv[k] = nb_cur[k];
+            if (s2 + 1 < NMS) {
+                gather(s2 + 1, vm_nxt, nb_cur);
+                vm_cur = vm_nxt;
+                if (s2 + 2 < NMS) vm_nxt = vmg[(s2 + 2) * 64];
+            }
             T fl[NF];
 #pragma unroll
             for (int k = 0; k < NF; ++k) fl[k] = T(0);
             const int vm = s_slot[2 * m];
             if (valid && vm >= 0) {
                 const int f = s_slot[2 * m + 1];
-                const int32_t idx = a.vmapP[int64_t(g) * (O::slots() * 16) + m * 16 + col];
                 T y[NF];
                 if (idx >= 0) {
-                    const int e2 = idx / NP;
-                    const int j2 = idx - e2 * NP;
-                    const int64_t nb = (int64_t(e2 >> 4) * (NF * NP) + j2) * 16 + (e2 & 15);
 #pragma unroll
-                    for (int k = 0; k < NF; ++k)
-                        y[k] = own(k, vm) - stage_in_at<NCONS, STAGE, T>(a.Q, a.A, a.B, kc, k, nb + k * NP * 16);
+                    for (int k = 0; k < NF; ++k) y[k] = own(k, vm) - nbv[k];
                 } else if (idx == -1) {
 #pragma unroll
                     for (int k = 0; k < NF; ++k) y[k] = T(0);
@@ -419,31 +500,44 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
                     for (int v = 0; v < NVERT; ++v) wd += BARY[vm * NVERT + v] * wvt[v * DIM + d];
                     wn += wd * nv[d];
                 }
-                T gl[5];
-                {
+                if (kc.flux_mode == 0) {
+                    // split upwinding: (c M_n)^- y + min(-w.n, 0) y, the first
+                    // part by Horner's scheme in M_n with solver constants
+#pragma unroll
+                    for (int k = 0; k < NF; ++k) fl[k] = kc.fluxA[4] * y[k];
+#pragma unroll
+                    for (int p = 3; p >= 0; --p) {
+                        T z[NF];
+                        apply_Mn<DIM, T>(nv, fl, z);
+                        const T ap = p == 0 ? kc.fluxA[0] + tmin(-wn, T(0)) : kc.fluxA[p];
+#pragma unroll
+                        for (int k = 0; k < NF; ++k) fl[k] = z[k] + ap * y[k];
+                    }
+                } else {
+                    // relative upwinding: weights min(c lambda - w.n, 0) on the
+                    // spectrum, turned into polynomial coefficients per node
+                    T gl[5];
                     const T cs3 = kc.c * T(1.7320508075688772);
                     const T lam[5] = {-cs3, -kc.c, T(0), kc.c, cs3};
-                    const T wneg = tmin(-wn, T(0));
 #pragma unroll
-                    for (int l = 0; l < 5; ++l)
-                        gl[l] = kc.flux_mode == 0 ? tmin(lam[l], T(0)) + wneg : tmin(lam[l] - wn, T(0));
-                }
-                T cp = T(0);
+                    for (int l = 0; l < 5; ++l) gl[l] = tmin(lam[l] - wn, T(0));
+                    T cp = T(0);
 #pragma unroll
-                for (int l = 0; l < 5; ++l) cp += kc.fluxV[l] * gl[l];
+                    for (int l = 0; l < 5; ++l) cp += kc.fluxV[l] * gl[l];
 #pragma unroll
-                for (int k = 0; k < NF; ++k) fl[k] = cp * y[k];
+                    for (int k = 0; k < NF; ++k) fl[k] = cp * y[k];
 #pragma unroll
-                for (int p = 1; p < 5; ++p) {
-                    T z[NF];
-                    apply_Mn<DIM, T>(nv, y, z);
-                    cp = T(0);
+                    for (int p = 1; p < 5; ++p) {
+                        T z[NF];
+                        apply_Mn<DIM, T>(nv, y, z);
+                        cp = T(0);
 #pragma unroll
-                    for (int l = 0; l < 5; ++l) cp += kc.fluxV[p * 5 + l] * gl[l];
+                        for (int l = 0; l < 5; ++l) cp += kc.fluxV[p * 5 + l] * gl[l];
 #pragma unroll
-                    for (int k = 0; k < NF; ++k) {
-                        y[k] = z[k];
-                        fl[k] += cp * z[k];
+                        for (int k = 0; k < NF; ++k) {
+                            y[k] = z[k];
+                            fl[k] += cp * z[k];
+                        }
                     }
                 }
 #pragma unroll
@@ -456,6 +550,16 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
         }
 
         // ---- sponge, SARK-4 stage combination and store (this lane's rows)
+        double spx[NVERT][2];
+        if constexpr (DIM == 2) {
+            if (kc.sponge) {
+#pragma unroll
+                for (int v = 0; v < NVERT; ++v) {
+                    spx[v][0] = a.xs[int64_t(vid[v]) * DIM + 0];
+                    spx[v][1] = a.xs[int64_t(vid[v]) * DIM + 1];
+                }
+            }
+        }
 #pragma unroll
         for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
@@ -468,10 +572,10 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
                 if constexpr (DIM == 2) {
                     if (kc.sponge) {
                         double px = 0.0, py = 0.0;
+#pragma unroll
                         for (int v = 0; v < NVERT; ++v) {
-                            const int64_t gv = a.etov[e * NVERT + v];
-                            px += double(BARY[i * NVERT + v]) * a.xs[gv * DIM + 0];
-                            py += double(BARY[i * NVERT + v]) * a.xs[gv * DIM + 1];
+                            px += double(BARY[i * NVERT + v]) * spx[v][0];
+                            py += double(BARY[i * NVERT + v]) * spx[v][1];
                         }
                         const double rr = sqrt((px - kc.sp_cx) * (px - kc.sp_cx) + (py - kc.sp_cy) * (py - kc.sp_cy));
                         double xi = (rr - kc.sp_r0) / (kc.sp_r1 - kc.sp_r0);
@@ -503,6 +607,9 @@ __global__ void __launch_bounds__(256) stage_mfma_kernel(KArgs<T> a) {
                     }
                 }
             }
+        // every lane is done with this wave's LDS block before the next group
+        // overwrites it
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
