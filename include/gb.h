@@ -49,7 +49,8 @@ typedef enum {
     GB_ERR_DEVICE = 4,       /* HIP runtime error                                 */
     GB_ERR_NONPHYSICAL = 5,  /* latched on the device: density <= 0 or NaN        */
     GB_ERR_STATE = 6,        /* call out of order (e.g. stepping without a state) */
-    GB_ERR_UNSUPPORTED = 7   /* (dim, N, precision) combination not built         */
+    GB_ERR_UNSUPPORTED = 7,  /* (dim, N, precision) combination not built         */
+    GB_ERR_BUSY = 8          /* admission refused: over the batch's free budget   */
 } gb_status;
 
 typedef enum { GB_FP64 = 0, GB_FP32 = 1 } gb_precision;
@@ -112,6 +113,7 @@ typedef struct {
 typedef struct gb_ctx gb_ctx;
 typedef struct gb_mesh gb_mesh;
 typedef struct gb_solver gb_solver;
+typedef struct gb_batch gb_batch;
 
 /* Last error message of this thread (never NULL). */
 const char *gb_last_error(void);
@@ -174,8 +176,12 @@ gb_status gb_solver_create(gb_mesh *mesh, const gb_params *params, gb_solver **o
 void gb_solver_destroy(gb_solver *solver);
 
 /* Device bytes gb_solver_create would allocate for this mesh and params
- * (state arrays only; the mesh's own tables are counted by the mesh). */
+ * (state arrays and per-stage vertex data; the mesh's own tables are counted
+ * by gb_mesh_footprint). */
 gb_status gb_solver_footprint(const gb_mesh *mesh, const gb_params *params, size_t *bytes);
+
+/* Device bytes held by the mesh (connectivity, trace map, vertex arrays). */
+gb_status gb_mesh_footprint(const gb_mesh *mesh, size_t *bytes);
 
 /* Set the state q [K][NF][Np] (FP64 host) and the time t0. */
 gb_status gb_state_set(gb_solver *solver, const double *q, double t0);
@@ -208,6 +214,59 @@ gb_status gb_solver_time_stages(gb_solver *solver, int enable);
 gb_status gb_solver_stage_time(gb_solver *solver, double *avg_ms, int64_t *launches);
 /* Per stage kind (0..3) average launch duration in ms, same measurement. */
 gb_status gb_solver_stage_time_by_kind(gb_solver *solver, double *avg_ms4);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many solvers (meshes of any size, orders and precisions on
+ * one device) advanced together.  Each step of the batch is one captured HIP
+ * graph: a vertex-motion launch per dimension, then for each of the four
+ * SARK-4 stages one stage launch per class (same dimension, order, precision
+ * and cubature rule) over the concatenated element groups of its members,
+ * then the end-of-step vertex update.  The kernels read a device request
+ * table (buffers, group offsets, constants, clock and target step of every
+ * member); a member whose step counter has reached its target is skipped, so
+ * members finish at different steps while the graph keeps replaying.  The
+ * arithmetic per element is the same code as gb_sark_step, so a member's
+ * result does not depend on what else is in the batch.
+ *
+ * Continuous batching: members join (gb_batch_add) and leave (gb_batch_poll)
+ * at step boundaries; the table and the graph are rebuilt at the next
+ * gb_batch_run after a change.  The launch grid of each class is chosen by
+ * timing the first stage at several grids the first time the class runs
+ * (stage 0 at a step boundary only overwrites a buffer the next step
+ * recomputes, so the tuning leaves every member's state unchanged).
+ * ------------------------------------------------------------------------ */
+
+/* Create a batch on ctx's stream with an admission budget in bytes of device
+ * memory (the sum of gb_solver_footprint + gb_mesh_footprint of its members). */
+gb_status gb_batch_create(gb_ctx *ctx, size_t hbm_budget, gb_batch **out);
+/* Synchronises; the members stay valid and owned by the caller. */
+void gb_batch_destroy(gb_batch *batch);
+
+/* Admit solver (state already set, same device) for nsteps >= 1 more steps of
+ * size dt.  GB_ERR_BUSY if its footprint exceeds the free budget (nothing is
+ * changed; retry after members leave).  The solver must not be stepped or
+ * read by other calls until gb_batch_poll has returned its ticket. */
+gb_status gb_batch_add(gb_batch *batch, gb_solver *solver, double dt, int64_t nsteps, uint64_t *ticket);
+
+/* Enqueue `steps` batch steps on the batch's stream (asynchronous). */
+gb_status gb_batch_run(gb_batch *batch, int64_t steps);
+
+/* Synchronise, retire up to `capacity` members that reached their target
+ * step and write their tickets to done[0..*n_done).  A retired solver is
+ * usable alone again (gb_state_get reports its time, steps and latched
+ * errors). */
+gb_status gb_batch_poll(gb_batch *batch, uint64_t *done, int capacity, int *n_done);
+
+/* Members, budget in use, and budget. */
+gb_status gb_batch_info(const gb_batch *batch, int *active, size_t *used_bytes, size_t *budget);
+
+/* Enable (default) or disable the launch-grid tuning of new classes. */
+gb_status gb_batch_set_autotune(gb_batch *batch, int enable);
+
+/* Classes of the current table (valid after gb_batch_run): info[6] =
+ * {dim, N, precision, members, element groups, launch grid}. */
+gb_status gb_batch_class_count(const gb_batch *batch, int *n);
+gb_status gb_batch_class_info(const gb_batch *batch, int i, int64_t *info6);
 
 #ifdef __cplusplus
 }

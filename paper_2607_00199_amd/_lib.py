@@ -15,14 +15,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgb.so")
 
-GB_OK, GB_ERR_ARG, GB_ERR_MESH, GB_ERR_OOM, GB_ERR_DEVICE, GB_ERR_NONPHYSICAL, GB_ERR_STATE, GB_ERR_UNSUPPORTED = range(8)
+(GB_OK, GB_ERR_ARG, GB_ERR_MESH, GB_ERR_OOM, GB_ERR_DEVICE, GB_ERR_NONPHYSICAL, GB_ERR_STATE, GB_ERR_UNSUPPORTED,
+ GB_ERR_BUSY) = range(9)
 GB_FP64, GB_FP32 = 0, 1
 GB_FLUX_SPLIT, GB_FLUX_RELATIVE = 0, 1
 GB_FACE_INTERIOR, GB_FACE_WALL, GB_FACE_FARFIELD = 0, 1, 2
 GB_MOTION_NONE, GB_MOTION_SIN_PRODUCT_2D, GB_MOTION_TRIPLE_PRODUCT_3D, GB_MOTION_PLUNGE_BLEND_2D = range(4)
 
 STATUS_NAMES = {0: "GB_OK", 1: "GB_ERR_ARG", 2: "GB_ERR_MESH", 3: "GB_ERR_OOM", 4: "GB_ERR_DEVICE",
-                5: "GB_ERR_NONPHYSICAL", 6: "GB_ERR_STATE", 7: "GB_ERR_UNSUPPORTED"}
+                5: "GB_ERR_NONPHYSICAL", 6: "GB_ERR_STATE", 7: "GB_ERR_UNSUPPORTED", 8: "GB_ERR_BUSY"}
 
 
 class GbError(RuntimeError):
@@ -73,6 +74,16 @@ SIGNATURES = {
     "gb_solver_time_stages": (C.c_int, [_P, C.c_int]),
     "gb_solver_stage_time": (C.c_int, [_P, _dp, C.POINTER(_i64)]),
     "gb_solver_stage_time_by_kind": (C.c_int, [_P, _dp]),
+    "gb_mesh_footprint": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "gb_batch_create": (C.c_int, [_P, C.c_size_t, C.POINTER(_P)]),
+    "gb_batch_destroy": (None, [_P]),
+    "gb_batch_add": (C.c_int, [_P, _P, C.c_double, _i64, C.POINTER(C.c_uint64)]),
+    "gb_batch_run": (C.c_int, [_P, _i64]),
+    "gb_batch_poll": (C.c_int, [_P, C.POINTER(C.c_uint64), C.c_int, C.POINTER(C.c_int)]),
+    "gb_batch_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "gb_batch_set_autotune": (C.c_int, [_P, C.c_int]),
+    "gb_batch_class_count": (C.c_int, [_P, C.POINTER(C.c_int)]),
+    "gb_batch_class_info": (C.c_int, [_P, C.c_int, C.POINTER(_i64)]),
 }
 
 _lib = None
@@ -251,3 +262,60 @@ def gb_solver_stage_time_by_kind(solver):
     out = np.zeros(4)
     _check(load().gb_solver_stage_time_by_kind(solver, _dptr(out)))
     return out
+
+
+def gb_mesh_footprint(mesh) -> int:
+    n = C.c_size_t()
+    _check(load().gb_mesh_footprint(mesh, C.byref(n)))
+    return n.value
+
+
+def gb_batch_create(ctx, hbm_budget: int):
+    out = _P()
+    _check(load().gb_batch_create(ctx, int(hbm_budget), C.byref(out)))
+    return out
+
+
+def gb_batch_destroy(batch):
+    load().gb_batch_destroy(batch)
+
+
+def gb_batch_add(batch, solver, dt: float, nsteps: int) -> int:
+    """Ticket of the admitted solver; raises GbError with status GB_ERR_BUSY
+    when it does not fit the free budget."""
+    t = C.c_uint64()
+    _check(load().gb_batch_add(batch, solver, dt, nsteps, C.byref(t)))
+    return t.value
+
+
+def gb_batch_run(batch, steps: int):
+    _check(load().gb_batch_run(batch, steps))
+
+
+def gb_batch_poll(batch, capacity: int = 1024) -> list:
+    buf = (C.c_uint64 * max(capacity, 1))()
+    n = C.c_int()
+    _check(load().gb_batch_poll(batch, buf, capacity, C.byref(n)))
+    return [int(buf[i]) for i in range(n.value)]
+
+
+def gb_batch_info(batch):
+    a, u, b = C.c_int(), C.c_size_t(), C.c_size_t()
+    _check(load().gb_batch_info(batch, C.byref(a), C.byref(u), C.byref(b)))
+    return a.value, u.value, b.value
+
+
+def gb_batch_set_autotune(batch, enable: bool):
+    _check(load().gb_batch_set_autotune(batch, 1 if enable else 0))
+
+
+def gb_batch_class_count(batch) -> int:
+    n = C.c_int()
+    _check(load().gb_batch_class_count(batch, C.byref(n)))
+    return n.value
+
+
+def gb_batch_class_info(batch, i: int) -> dict:
+    out = (_i64 * 6)()
+    _check(load().gb_batch_class_info(batch, i, out))
+    return dict(zip(("dim", "N", "precision", "members", "groups", "grid"), (int(v) for v in out)))

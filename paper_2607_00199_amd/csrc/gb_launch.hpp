@@ -30,10 +30,30 @@ struct LaunchArgs {
     int *err = nullptr;
 };
 
+// One stage launch of the batched form over a request table.
+struct BatchLaunch {
+    const void *ent = nullptr;         // BatchEntry<T>[nreq] in device memory
+    const int32_t *group_begin = nullptr;
+    int nreq = 0;
+    int64_t total = 0;                 // element groups over all entries
+    int Nc = 0;
+    int grid = 1;                      // workgroups to aim for
+    size_t lds = 0;                    // dynamic LDS bytes (batch_lds of nreq)
+    const void *ops = nullptr;
+    const int32_t *fmask = nullptr;
+};
+
 struct ShapeEntry {
     hipError_t (*stage)(const LaunchArgs &, int kind, hipStream_t);
     size_t (*lds)(int Nc);
     int (*ops_total)(int Nc);
+    // batched form; null for the shapes it is not built for
+    hipError_t (*batch_stage)(const BatchLaunch &, int kind, hipStream_t);
+    size_t (*batch_lds)(int Nc, int nreq);
+    // raises the dynamic-LDS limit of the batched kernels (outside capture)
+    hipError_t (*batch_allow_lds)(size_t bytes);
+    // largest per-lane scratch of the batched kernels (0 expected)
+    hipError_t (*batch_scratch)(size_t *bytes);
 };
 
 // Stage kinds 0..3 are the SARK-4 stages, 4 the plain right-hand side.
@@ -83,13 +103,85 @@ hipError_t launch_stage(const LaunchArgs &L, int kind, hipStream_t st) {
 }
 
 template <int DIM, int N, typename T>
+hipError_t launch_stage_batch(const BatchLaunch &L, int kind, hipStream_t st) {
+    BatchArgs<T> b{};
+    b.ent = static_cast<const BatchEntry<T> *>(L.ent);
+    b.group_begin = L.group_begin;
+    b.nreq = L.nreq;
+    b.total = int(L.total);
+    b.Nc = L.Nc;
+    b.ops = static_cast<const T *>(L.ops);
+    b.fmask = L.fmask;
+    int grid = int(std::min<int64_t>(L.grid, (L.total + kWaves - 1) / kWaves));
+    if (grid < 1) grid = 1;
+    if (grid >= 8) grid = grid / 8 * 8;
+    b.chunk = int((L.total + grid - 1) / grid);
+    grid = int((L.total + b.chunk - 1) / b.chunk);
+    if (grid >= 8 && grid % 8) grid = (grid + 7) / 8 * 8;
+    using K0 = decltype(&stage_batch_kernel<DIM, N, T, 0>);
+    const K0 fns[5] = {&stage_batch_kernel<DIM, N, T, 0>, &stage_batch_kernel<DIM, N, T, 1>,
+                       &stage_batch_kernel<DIM, N, T, 2>, &stage_batch_kernel<DIM, N, T, 3>,
+                       &stage_batch_kernel<DIM, N, T, 4>};
+    hipLaunchKernelGGL(fns[kind < 4 ? kind : 4], dim3(grid), dim3(64 * kWaves), L.lds, st, b);
+    return hipGetLastError();
+}
+
+template <int DIM, int N, typename T>
+void batch_kernels(const void *out[5]) {
+    out[0] = (const void *)&stage_batch_kernel<DIM, N, T, 0>;
+    out[1] = (const void *)&stage_batch_kernel<DIM, N, T, 1>;
+    out[2] = (const void *)&stage_batch_kernel<DIM, N, T, 2>;
+    out[3] = (const void *)&stage_batch_kernel<DIM, N, T, 3>;
+    out[4] = (const void *)&stage_batch_kernel<DIM, N, T, 4>;
+}
+
+template <int DIM, int N, typename T>
+hipError_t batch_allow_lds(size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    const void *fns[5];
+    batch_kernels<DIM, N, T>(fns);
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int DIM, int N, typename T>
+hipError_t batch_scratch(size_t *bytes) {
+    const void *fns[5];
+    batch_kernels<DIM, N, T>(fns);
+    *bytes = 0;
+    for (const void *f : fns) {
+        hipFuncAttributes attr;
+        hipError_t e = hipFuncGetAttributes(&attr, f);
+        if (e != hipSuccess) return e;
+        *bytes = std::max(*bytes, size_t(attr.localSizeBytes));
+    }
+    return hipSuccess;
+}
+
+template <int DIM, int N, typename T>
+size_t stage_batch_lds(int Nc, int nreq) { return batch_lds_bytes<DIM, N, T>((Nc + 15) / 16, nreq); }
+
+template <int DIM, int N, typename T>
 size_t stage_lds(int Nc) { return mfma_lds_bytes<DIM, N, T>((Nc + 15) / 16); }
 
 template <int DIM, int N>
 int stage_ops_total(int Nc) { return MOps<DIM, N>::total((Nc + 15) / 16); }
 
 template <int DIM, int N, typename T>
-ShapeEntry shape_entry() { return ShapeEntry{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N>}; }
+ShapeEntry shape_entry() {
+    ShapeEntry s{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N>, nullptr, nullptr, nullptr,
+                 nullptr};
+    if constexpr (batch_enabled<DIM, N, T>()) {
+        s.batch_stage = &launch_stage_batch<DIM, N, T>;
+        s.batch_lds = &stage_batch_lds<DIM, N, T>;
+        s.batch_allow_lds = &batch_allow_lds<DIM, N, T>;
+        s.batch_scratch = &batch_scratch<DIM, N, T>;
+    }
+    return s;
+}
 
 }  // namespace gbd
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -214,6 +216,28 @@ bool get_launcher(int dim, int N, int prec, Launcher &L) {
     return false;
 }
 
+// Request-table entry of a solver for the batched form.
+template <typename T>
+gbd::BatchEntry<T> make_entry(const gb_solver *s, double target) {
+    const gb_mesh *m = s->mesh;
+    gbd::BatchEntry<T> e{};
+    e.K = m->K;
+    e.nv = m->nv;
+    e.etov = m->d_etov.as<int32_t>();
+    e.vstage = s->vstage.as<double>();
+    e.wstage = s->wstage.as<double>();
+    e.vmapP = m->d_vmapP.as<int32_t>();
+    e.Q = s->Q.as<T>();
+    e.A = s->A.as<T>();
+    e.B = s->B.as<T>();
+    e.G = s->G.as<T>();
+    e.clock = s->clock.as<double>();
+    e.kc = s->kconst.as<gbd::KConst<T>>();
+    e.err = s->err.as<int>();
+    e.target = target;
+    return e;
+}
+
 hipError_t Launcher::stage(gb_solver *s, int kind, double dt, hipStream_t st) const {
     (void)dt;
     const gb_mesh *m = s->mesh;
@@ -353,6 +377,259 @@ gb_status enqueue_step(gb_solver *s, const Launcher &L, double dt, hipStream_t s
         hipLaunchKernelGGL(gbd::finish_step_kernel<3>, dim3(nb), dim3(blk), 0, st, m->nv, m->d_x.as<double>(), xnext,
                            s->clock.as<double>(), dt);
     GB_HIP(hipGetLastError());
+    return GB_OK;
+}
+
+}  // namespace
+
+// ================================================================= batched form
+
+struct gb_batch {
+    gb_ctx *ctx = nullptr;
+    size_t budget = 0, used = 0;
+    uint64_t next_ticket = 1;
+    bool autotune = true;
+    struct Member {
+        gb_solver *s = nullptr;
+        double dt = 0.0;
+        double target = 0.0;        // step count at which the member stops
+        uint64_t ticket = 0;
+        size_t bytes = 0;
+    };
+    std::vector<Member> members;
+    struct Class {
+        int dim = 2, N = 1, prec = 0, Nc = 0;
+        std::vector<int> idx;       // member indices
+        gbd::ShapeEntry shape{};
+        DevBuf ent, gbeg;
+        int nreq = 0;
+        int64_t total = 0;          // element groups
+        size_t lds = 0;
+        int grid = 0;
+        const void *ops = nullptr;
+        const int32_t *fmask = nullptr;
+    };
+    std::vector<Class> classes;
+    DevBuf mot[2];                  // gbd::MotionEntry tables, 2D and 3D
+    int nmot[2] = {0, 0};
+    int64_t vtot[2] = {0, 0};
+    std::map<std::array<int, 4>, int> tuned;   // (dim, N, precision, Nc) -> grid
+    hipGraphExec_t graph = nullptr;
+    bool dirty = true;
+    ~gb_batch() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
+};
+
+namespace {
+
+size_t mesh_bytes(const gb_mesh *m) { return m->d_etov.bytes + m->d_X.bytes + m->d_x.bytes + m->d_vmapP.bytes; }
+
+size_t solver_bytes(const gb_mesh *m, const gb_params *p) {
+    const size_t es = p->precision == GB_FP32 ? 4 : 8;
+    return 4 * size_t((m->K + 15) / 16 * 16) * n_fields(m->dim) * m->ref.Np * es +
+           (5 + 4) * size_t(m->nv) * m->dim * sizeof(double);
+}
+
+template <typename T>
+gb_status upload_class_table(gb_batch *b, gb_batch::Class &c) {
+    std::vector<gbd::BatchEntry<T>> ent(c.idx.size());
+    std::vector<int32_t> gb(c.idx.size());
+    int64_t g = 0;
+    for (size_t i = 0; i < c.idx.size(); ++i) {
+        const gb_batch::Member &mb = b->members[size_t(c.idx[i])];
+        gb_solver *s = mb.s;
+        gb_mesh *m = s->mesh;
+        ent[i] = make_entry<T>(s, mb.target);
+        gb[i] = int32_t(g);
+        g += (m->K + 15) / 16;
+    }
+    if (g >= (int64_t(1) << 31)) return fail(GB_ERR_UNSUPPORTED, "too many element groups in one class");
+    c.total = g;
+    if (c.ent.alloc(ent.size() * sizeof(ent[0])) != hipSuccess || c.gbeg.alloc(gb.size() * sizeof(int32_t)) != hipSuccess)
+        return fail(GB_ERR_OOM, "batch request table");
+    GB_HIP(hipMemcpy(c.ent.p, ent.data(), c.ent.bytes, hipMemcpyHostToDevice));
+    GB_HIP(hipMemcpy(c.gbeg.p, gb.data(), c.gbeg.bytes, hipMemcpyHostToDevice));
+    return GB_OK;
+}
+
+gbd::BatchLaunch class_launch(const gb_batch::Class &c, int grid) {
+    gbd::BatchLaunch L;
+    L.ent = c.ent.p;
+    L.group_begin = c.gbeg.as<int32_t>();
+    L.nreq = c.nreq;
+    L.total = c.total;
+    L.Nc = c.Nc;
+    L.grid = grid;
+    L.lds = c.lds;
+    L.ops = c.ops;
+    L.fmask = c.fmask;
+    return L;
+}
+
+hipError_t launch_vertex_batch(gb_batch *b, int di, bool finish, hipStream_t st) {
+    if (b->nmot[di] == 0) return hipSuccess;
+    const int blk = 256;
+    const unsigned nb = unsigned((b->vtot[di] + blk - 1) / blk);
+    const gbd::MotionEntry *E = b->mot[di].as<gbd::MotionEntry>();
+    if (di == 0) {
+        if (finish)
+            hipLaunchKernelGGL(gbd::finish_batch_kernel<2>, dim3(nb), dim3(blk), 0, st, E, b->nmot[0], b->vtot[0]);
+        else
+            hipLaunchKernelGGL(gbd::motion_batch_kernel<2>, dim3(nb), dim3(blk), 0, st, E, b->nmot[0], b->vtot[0]);
+    } else {
+        if (finish)
+            hipLaunchKernelGGL(gbd::finish_batch_kernel<3>, dim3(nb), dim3(blk), 0, st, E, b->nmot[1], b->vtot[1]);
+        else
+            hipLaunchKernelGGL(gbd::motion_batch_kernel<3>, dim3(nb), dim3(blk), 0, st, E, b->nmot[1], b->vtot[1]);
+    }
+    return hipGetLastError();
+}
+
+// Launch grid of a class: the fastest of a few workgroup counts for stage 0,
+// timed on the members' current state (see gb.h: state is not changed).
+gb_status tune_class(gb_batch *b, gb_batch::Class &c) {
+    hipStream_t st = b->ctx->stream;
+    GB_HIP(launch_vertex_batch(b, c.dim - 2, false, st));
+    const int mults[5] = {1, 2, 4, 8, 16};
+    hipEvent_t e0, e1;
+    GB_HIP(hipEventCreate(&e0));
+    GB_HIP(hipEventCreate(&e1));
+    int best = b->ctx->num_cu * 8;
+    float best_ms = 1e30f;
+    gb_status r = GB_OK;
+    for (int mi = 0; mi < 5 && r == GB_OK; ++mi) {
+        const int grid = b->ctx->num_cu * mults[mi];
+        const gbd::BatchLaunch L = class_launch(c, grid);
+        hipError_t e = c.shape.batch_stage(L, 0, st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = c.shape.batch_stage(L, 0, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            r = fail(GB_ERR_DEVICE, std::string("batch tuning: ") + hipGetErrorString(e));
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = grid;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r == GB_OK) c.grid = best;
+    return r;
+}
+
+gb_status batch_rebuild(gb_batch *b) {
+    hipStream_t st = b->ctx->stream;
+    GB_HIP(hipSetDevice(b->ctx->device));
+    GB_HIP(hipStreamSynchronize(st));   // queued replays may still read the old tables
+    if (b->graph) {
+        GB_HIP(hipGraphExecDestroy(b->graph));
+        b->graph = nullptr;
+    }
+    b->classes.clear();
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        const gb_solver *s = b->members[i].s;
+        const int dim = s->mesh->dim, N = s->mesh->N, prec = s->prm.precision, Nc = s->ref.Nc;
+        gb_batch::Class *c = nullptr;
+        for (auto &cc : b->classes)
+            if (cc.dim == dim && cc.N == N && cc.prec == prec && cc.Nc == Nc) c = &cc;
+        if (!c) {
+            b->classes.emplace_back();
+            c = &b->classes.back();
+            c->dim = dim;
+            c->N = N;
+            c->prec = prec;
+            c->Nc = Nc;
+        }
+        c->idx.push_back(int(i));
+    }
+    for (auto &c : b->classes) {
+        Launcher L;
+        if (!get_launcher(c.dim, c.N, c.prec, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel for a batch class");
+        c.shape = L.shape;
+        c.nreq = int(c.idx.size());
+        if (c.nreq > gbd::kMaxBatch) return fail(GB_ERR_UNSUPPORTED, "too many members in one class");
+        const gb_status r = c.prec == GB_FP64 ? upload_class_table<double>(b, c) : upload_class_table<float>(b, c);
+        if (r != GB_OK) return r;
+        c.lds = c.shape.batch_lds(c.Nc, c.nreq);
+        if (c.lds > b->ctx->max_lds) return fail(GB_ERR_UNSUPPORTED, "batch class exceeds the LDS of one workgroup");
+        GB_HIP(c.shape.batch_allow_lds(c.lds));
+        const gb_solver *s0 = b->members[size_t(c.idx[0])].s;
+        c.ops = s0->ops.p;
+        c.fmask = s0->fmask.as<int32_t>();
+        auto it = b->tuned.find({c.dim, c.N, c.prec, c.Nc});
+        c.grid = it != b->tuned.end() ? it->second : b->ctx->num_cu * 8;
+    }
+    for (int di = 0; di < 2; ++di) {
+        std::vector<gbd::MotionEntry> E;
+        int64_t v = 0;
+        for (const auto &mb : b->members) {
+            const gb_solver *s = mb.s;
+            const gb_mesh *m = s->mesh;
+            if (m->dim != di + 2) continue;
+            gbd::MotionEntry e{};
+            e.nv = m->nv;
+            e.v_begin = v;
+            e.X = m->d_X.as<double>();
+            e.x = m->d_x.as<double>();
+            e.clock = s->clock.as<double>();
+            e.vstage = s->vstage.as<double>();
+            e.wstage = s->wstage.as<double>();
+            e.dt = mb.dt;
+            e.target = mb.target;
+            e.m = m->motion;
+            E.push_back(e);
+            v += m->nv;
+        }
+        if (int(E.size()) > gbd::kMaxBatch) return fail(GB_ERR_UNSUPPORTED, "too many members of one dimension");
+        b->nmot[di] = int(E.size());
+        b->vtot[di] = v;
+        if (!E.empty()) {
+            if (b->mot[di].alloc(E.size() * sizeof(E[0])) != hipSuccess) return fail(GB_ERR_OOM, "motion table");
+            GB_HIP(hipMemcpy(b->mot[di].p, E.data(), b->mot[di].bytes, hipMemcpyHostToDevice));
+        }
+    }
+    if (b->autotune)
+        for (auto &c : b->classes) {
+            const std::array<int, 4> key{c.dim, c.N, c.prec, c.Nc};
+            if (b->tuned.count(key)) continue;
+            const gb_status r = tune_class(b, c);
+            if (r != GB_OK) return r;
+            b->tuned[key] = c.grid;
+        }
+    if (b->members.empty()) {
+        b->dirty = false;
+        return GB_OK;
+    }
+    // one step as a graph, captured on a private stream
+    hipStream_t cap;
+    GB_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipSuccess;
+        for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, di, false, cap);
+        for (int kind = 0; kind < 4 && le == hipSuccess; ++kind)
+            for (auto &c : b->classes)
+                if (le == hipSuccess) le = c.shape.batch_stage(class_launch(c, c.grid), kind, cap);
+        for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, di, true, cap);
+        e = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess && le != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            e = le;
+        }
+    }
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(GB_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(GB_ERR_DEVICE, std::string("batch graph instantiate: ") + hipGetErrorString(e));
+    b->dirty = false;
     return GB_OK;
 }
 
@@ -540,9 +817,13 @@ gb_status gb_set_motion(gb_mesh *m, const gb_motion *mo) {
 
 gb_status gb_solver_footprint(const gb_mesh *m, const gb_params *p, size_t *bytes) {
     if (!m || !p || !bytes) return fail(GB_ERR_ARG, "NULL argument");
-    const size_t es = p->precision == GB_FP32 ? 4 : 8;
-    *bytes = 4 * size_t((m->K + 15) / 16 * 16) * n_fields(m->dim) * m->ref.Np * es +
-             (5 + 4) * size_t(m->nv) * m->dim * sizeof(double);
+    *bytes = solver_bytes(m, p);
+    return GB_OK;
+}
+
+gb_status gb_mesh_footprint(const gb_mesh *m, size_t *bytes) {
+    if (!m || !bytes) return fail(GB_ERR_ARG, "NULL argument");
+    *bytes = mesh_bytes(m);
     return GB_OK;
 }
 
@@ -599,6 +880,7 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     GB_HIP(hipMemset(s->err.p, 0, sizeof(int)));
     double clk[2] = {0.0, 0.0};
     GB_HIP(hipMemcpy(s->clock.p, clk, sizeof(clk), hipMemcpyHostToDevice));
+
     ++m->solvers;
     *out = s.release();
     return GB_OK;
@@ -821,6 +1103,132 @@ gb_status gb_solver_stage_time_by_kind(gb_solver *s, double *avg_ms4) {
     gb_status r = resolve_events(s);
     if (r != GB_OK) return r;
     for (int k = 0; k < 4; ++k) avg_ms4[k] = s->launches_kind[k] ? s->time_ms_kind[k] / double(s->launches_kind[k]) : 0.0;
+    return GB_OK;
+}
+
+gb_status gb_batch_create(gb_ctx *ctx, size_t hbm_budget, gb_batch **out) {
+    if (!ctx || !out) return fail(GB_ERR_ARG, "NULL argument");
+    auto b = std::make_unique<gb_batch>();
+    b->ctx = ctx;
+    b->budget = hbm_budget;
+    *out = b.release();
+    return GB_OK;
+}
+
+void gb_batch_destroy(gb_batch *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    delete b;
+}
+
+gb_status gb_batch_add(gb_batch *b, gb_solver *s, double dt, int64_t nsteps, uint64_t *ticket) {
+    if (!b || !s || !ticket) return fail(GB_ERR_ARG, "NULL argument");
+    if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
+    if (!(dt > 0.0) || nsteps < 1) return fail(GB_ERR_ARG, "dt must be positive and nsteps >= 1");
+    gb_mesh *m = s->mesh;
+    if (m->ctx->device != b->ctx->device) return fail(GB_ERR_ARG, "solver lives on another device");
+    for (const auto &mb : b->members)
+        if (mb.s == s) return fail(GB_ERR_STATE, "solver is already in the batch");
+    if (int(b->members.size()) >= gbd::kMaxBatch) return fail(GB_ERR_BUSY, "batch is full");
+    const size_t bytes = solver_bytes(m, &s->prm) + mesh_bytes(m);
+    if (b->used + bytes > b->budget) return fail(GB_ERR_BUSY, "request does not fit the free budget of the batch");
+    Launcher L;
+    if (!get_launcher(m->dim, m->N, s->prm.precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel");
+    if (!L.shape.batch_stage)
+        return fail(GB_ERR_UNSUPPORTED, "the batched form is not built for this element shape and precision");
+    GB_HIP(hipSetDevice(m->ctx->device));
+    {
+        size_t scratch = 0;
+        GB_HIP(L.shape.batch_scratch(&scratch));
+        if (scratch) return fail(GB_ERR_UNSUPPORTED, "the batched kernel of this shape needs scratch memory");
+    }
+    GB_HIP(L.prepare(s, dt, m->ctx->stream));
+    double clk[2];
+    GB_HIP(hipMemcpyAsync(clk, s->clock.p, sizeof(clk), hipMemcpyDeviceToHost, m->ctx->stream));
+    GB_HIP(hipStreamSynchronize(m->ctx->stream));
+    gb_batch::Member mb;
+    mb.s = s;
+    mb.dt = dt;
+    mb.target = clk[1] + double(nsteps);
+    mb.ticket = b->next_ticket++;
+    mb.bytes = bytes;
+    b->members.push_back(mb);
+    b->used += bytes;
+    b->dirty = true;
+    *ticket = mb.ticket;
+    return GB_OK;
+}
+
+gb_status gb_batch_run(gb_batch *b, int64_t steps) {
+    if (!b) return fail(GB_ERR_ARG, "NULL batch");
+    if (steps < 0) return fail(GB_ERR_ARG, "steps must be >= 0");
+    if (b->dirty) {
+        const gb_status r = batch_rebuild(b);
+        if (r != GB_OK) return r;
+    }
+    if (b->members.empty() || steps == 0) return GB_OK;
+    GB_HIP(hipSetDevice(b->ctx->device));
+    for (int64_t k = 0; k < steps; ++k) GB_HIP(hipGraphLaunch(b->graph, b->ctx->stream));
+    return GB_OK;
+}
+
+gb_status gb_batch_poll(gb_batch *b, uint64_t *done, int capacity, int *n_done) {
+    if (!b || !n_done || (capacity > 0 && !done)) return fail(GB_ERR_ARG, "NULL argument");
+    *n_done = 0;
+    GB_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t st = b->ctx->stream;
+    std::vector<double> clk(2 * b->members.size());
+    for (size_t i = 0; i < b->members.size(); ++i)
+        GB_HIP(hipMemcpyAsync(&clk[2 * i], b->members[i].s->clock.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipStreamSynchronize(st));
+    std::vector<gb_batch::Member> keep;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        gb_batch::Member &mb = b->members[i];
+        if (clk[2 * i + 1] >= mb.target && *n_done < capacity) {
+            done[(*n_done)++] = mb.ticket;
+            mb.s->t = clk[2 * i];
+            mb.s->step = int64_t(clk[2 * i + 1]);
+            b->used -= mb.bytes;
+            b->dirty = true;
+        } else {
+            keep.push_back(mb);
+        }
+    }
+    b->members.swap(keep);
+    return GB_OK;
+}
+
+gb_status gb_batch_info(const gb_batch *b, int *active, size_t *used_bytes, size_t *budget) {
+    if (!b) return fail(GB_ERR_ARG, "NULL batch");
+    if (active) *active = int(b->members.size());
+    if (used_bytes) *used_bytes = b->used;
+    if (budget) *budget = b->budget;
+    return GB_OK;
+}
+
+gb_status gb_batch_set_autotune(gb_batch *b, int enable) {
+    if (!b) return fail(GB_ERR_ARG, "NULL batch");
+    b->autotune = enable != 0;
+    return GB_OK;
+}
+
+gb_status gb_batch_class_count(const gb_batch *b, int *n) {
+    if (!b || !n) return fail(GB_ERR_ARG, "NULL argument");
+    *n = int(b->classes.size());
+    return GB_OK;
+}
+
+gb_status gb_batch_class_info(const gb_batch *b, int i, int64_t *info) {
+    if (!b || !info) return fail(GB_ERR_ARG, "NULL argument");
+    if (i < 0 || i >= int(b->classes.size())) return fail(GB_ERR_ARG, "class index out of range");
+    const gb_batch::Class &c = b->classes[size_t(i)];
+    info[0] = c.dim;
+    info[1] = c.N;
+    info[2] = c.prec;
+    info[3] = c.nreq;
+    info[4] = c.total;
+    info[5] = c.grid;
     return GB_OK;
 }
 

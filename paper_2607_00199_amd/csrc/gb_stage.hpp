@@ -102,11 +102,8 @@ __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 // Writes xs[s][nv][DIM] for s = 0..4 (4 = end of step) and ws[s][nv][DIM]
 // for s = 0..3.
 template <int DIM>
-__global__ void motion_stages_kernel(int64_t nv, const double *X, const double *x, const double *clock, double dt,
-                                     Motion m, double *xs, double *ws) {
-    const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
-    const double tn = clock[0];
+__device__ __forceinline__ void motion_vertex(int64_t v, int64_t nv, const double *X, const double *x, double tn,
+                                              double dt, const Motion &m, double *xs, double *ws) {
     double Xv[DIM], xn[DIM], w0[DIM], w1[DIM], w2[DIM], w3[DIM];
     for (int d = 0; d < DIM; ++d) {
         Xv[d] = X[v * DIM + d];
@@ -131,6 +128,14 @@ __global__ void motion_stages_kernel(int64_t nv, const double *X, const double *
     }
 }
 
+template <int DIM>
+__global__ void motion_stages_kernel(int64_t nv, const double *X, const double *x, const double *clock, double dt,
+                                     Motion m, double *xs, double *ws) {
+    const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    motion_vertex<DIM>(v, nv, X, x, clock[0], dt, m, xs, ws);
+}
+
 // End of a step: x_n <- x_{n+1}; the first thread also advances the clock.
 template <int DIM>
 __global__ void finish_step_kernel(int64_t nv, double *x, const double *xnext, double *clock, double dt) {
@@ -140,6 +145,72 @@ __global__ void finish_step_kernel(int64_t nv, double *x, const double *xnext, d
     if (v == 0) {
         clock[0] = clock[0] + dt;
         clock[1] = clock[1] + 1.0;
+    }
+}
+
+// ---------------------------------------------------------------- batched form
+//
+// Many meshes stepped together: the vertex kernels of a step run over the
+// concatenated vertex ranges of every request of one dimension, found through
+// a request table.  A request whose step counter has reached its target is
+// left alone (its stage launches skip it as well), so a captured one-step
+// graph can be replayed while requests finish at different steps.
+
+constexpr int kMaxBatch = 1024;   // requests per table
+
+struct MotionEntry {
+    int64_t nv, v_begin;           // vertices, first vertex in the concatenation
+    const double *X;               // reference positions [nv][DIM]
+    double *x;                     // current positions
+    double *clock;                 // [t, step]
+    double *vstage, *wstage;       // [5][nv][DIM], [4][nv][DIM]
+    double dt, target;             // time step; step count at which the request stops
+    Motion m;
+};
+
+// Request owning vertex (or group) index i: largest r with begin[r] <= i.
+template <typename I>
+__device__ __forceinline__ int table_search(const I *begin, int n, I i) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int DIM>
+__global__ void motion_batch_kernel(const MotionEntry *E, int n, int64_t total) {
+    __shared__ int64_t s_vb[kMaxBatch];
+    for (int p = threadIdx.x; p < n; p += blockDim.x) s_vb[p] = E[p].v_begin;
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const MotionEntry &e = E[table_search(s_vb, n, i)];
+    if (e.clock[1] >= e.target) return;
+    const int64_t v = i - e.v_begin;
+    motion_vertex<DIM>(v, e.nv, e.X, e.x, e.clock[0], e.dt, e.m, e.vstage, e.wstage);
+}
+
+// x_n <- x_{n+1} for every request (a no-op for finished ones, whose stage
+// positions still hold their last end-of-step positions); the first vertex of
+// an unfinished request advances its clock.  Only that thread reads or writes
+// the clock, so the finished test cannot race with the advance.
+template <int DIM>
+__global__ void finish_batch_kernel(const MotionEntry *E, int n, int64_t total) {
+    __shared__ int64_t s_vb[kMaxBatch];
+    for (int p = threadIdx.x; p < n; p += blockDim.x) s_vb[p] = E[p].v_begin;
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const MotionEntry &e = E[table_search(s_vb, n, i)];
+    const int64_t v = i - e.v_begin;
+    const double *xnext = e.vstage + 4 * e.nv * DIM;
+    for (int d = 0; d < DIM; ++d) e.x[v * DIM + d] = xnext[v * DIM + d];
+    if (v == 0 && e.clock[1] < e.target) {
+        e.clock[0] = e.clock[0] + e.dt;
+        e.clock[1] = e.clock[1] + 1.0;
     }
 }
 

@@ -1,0 +1,245 @@
+"""Served form: a request loop over the batched C ABI.
+
+Requests (each a mesh, order, precision, parameters and a step count) arrive
+over time.  At every step boundary of the batch the loop
+
+  * admits arrived requests in arrival order while the request's device
+    footprint (gb_solver_footprint + gb_mesh_footprint) fits the free part of
+    the budget (a request that does not fit waits, and so does every request
+    behind it);
+  * runs the batch for a few steps (gb_batch_run, asynchronous; meshes of
+    newly arrived requests are built on the host meanwhile);
+  * retires the requests that reached their step count (gb_batch_poll) and
+    records completion - arrival as their latency.
+
+A request's state stays on the device from admission to completion.  This
+module only marshals arguments and keeps the books; every step of every
+request runs in libgb.so.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+from .session import equilibrium_moments, motion_params
+
+
+@dataclass
+class Request:
+    index: int
+    arrival: float                  # seconds after the start of serve()
+    case: object                    # a workloads Case
+    nsteps: int
+    precision: int = L.GB_FP32
+    keep_state: bool = False        # copy the final state to the host
+    # filled in by the server
+    bytes: int = 0
+    dof: int = 0
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    state: np.ndarray | None = None
+    t_final: float = math.nan
+    steps_done: int = 0
+    rejected: bool = False
+    _mesh: object = None
+    _solver: object = None
+    _params: object = None
+
+
+def admit_fifo(queue_bytes, free_bytes: int) -> int:
+    """Number of requests admitted from the head of a FIFO queue whose
+    footprints are queue_bytes, given free_bytes: stops at the first request
+    that does not fit (no overtaking)."""
+    n = 0
+    for b in queue_bytes:
+        if b > free_bytes:
+            break
+        free_bytes -= b
+        n += 1
+    return n
+
+
+def latency_summary(latencies) -> dict:
+    """p50 / p99 / max / mean of a list of latencies (seconds), nearest-rank
+    percentiles."""
+    x = np.sort(np.asarray(latencies, float))
+    if x.size == 0:
+        return {"n": 0, "p50": None, "p99": None, "max": None, "mean": None}
+
+    def pct(p):
+        k = max(1, int(math.ceil(p / 100.0 * x.size)))
+        return float(x[k - 1])
+
+    return {"n": int(x.size), "p50": pct(50), "p99": pct(99), "max": float(x[-1]), "mean": float(x.mean())}
+
+
+def case_params(case, precision):
+    """gb_params for a case: physical constants, and for cases with far-field
+    faces the free-stream equilibrium and the sponge layer."""
+    q_inf = sponge = None
+    if "u" in case.extra and case.face_tag is not None:
+        u = case.extra["u"]
+        q_inf = equilibrium_moments(case.dim, np.array(1.0), [np.array(v) for v in u], case.c)
+    if "sponge" in case.extra:
+        sponge = case.extra["sponge"]
+    return L.make_params(case.c, case.tau, precision, q_inf=q_inf, sponge=sponge)
+
+
+def initial_state(case, mesh) -> np.ndarray:
+    """Equilibrium moments of the case's initial macroscopic fields at the
+    mesh's nodes, [K, NF, Np]."""
+    X = L.gb_mesh_nodes(mesh, case.dim)
+    rho, u = case.macroscopic(X)
+    return equilibrium_moments(case.dim, rho, u, case.c).transpose(1, 0, 2).copy()
+
+
+class Server:
+    """One batch on one device, with a separate context (stream) for request
+    setup so that building and uploading a new request does not wait for the
+    batch's queued steps.  Pass non-blocking streams (e.g. torch.cuda.Stream
+    handles) for both."""
+
+    def __init__(self, budget_bytes: int, device: int = 0, run_stream: int = 0, setup_stream: int = 0,
+                 steps_per_launch: int = 5, autotune: bool = True):
+        self.run_ctx = L.gb_ctx_create(device, run_stream)
+        self.setup_ctx = L.gb_ctx_create(device, setup_stream)
+        self.batch = L.gb_batch_create(self.run_ctx, budget_bytes)
+        L.gb_batch_set_autotune(self.batch, autotune)
+        self.budget = int(budget_bytes)
+        self.steps_per_launch = int(steps_per_launch)
+        self.classes = []
+
+    # -------------------------------------------------------------- requests
+    def _prepare(self, r: Request):
+        c = r.case
+        r._mesh = L.gb_mesh_create(self.setup_ctx, c.dim, c.N, c.vx, c.etov, c.period, c.face_tag)
+        kind, p = motion_params(c.motion)
+        L.gb_set_motion(r._mesh, kind, p)
+        r._params = case_params(c, r.precision)
+        r.bytes = L.gb_solver_footprint(r._mesh, r._params) + L.gb_mesh_footprint(r._mesh)
+        K, Np, NF, _, _ = L.gb_mesh_sizes(r._mesh)
+        r.dof = K * Np * NF
+
+    def _start(self, r: Request) -> int:
+        r._solver = L.gb_solver_create(r._mesh, r._params)
+        L.gb_state_set(r._solver, initial_state(r.case, r._mesh))
+        return L.gb_batch_add(self.batch, r._solver, r.case.dt, r.nsteps)
+
+    def _finish(self, r: Request):
+        K, Np, NF, _, _ = L.gb_mesh_sizes(r._mesh)
+        q, t, step = L.gb_state_get(r._solver, (K, NF, Np))
+        r.t_final, r.steps_done = t, step
+        if r.keep_state:
+            r.state = q
+        self._release(r)
+
+    def _release(self, r: Request):
+        if r._solver is not None:
+            L.gb_solver_destroy(r._solver)
+            r._solver = None
+        if r._mesh is not None:
+            L.gb_mesh_destroy(r._mesh)
+            r._mesh = None
+
+    # -------------------------------------------------------------- loop
+    def serve(self, requests, clock=time.perf_counter, sleep=time.sleep) -> dict:
+        pend = deque(sorted(requests, key=lambda q: q.arrival))
+        queue: deque = deque()
+        active: dict = {}
+        finished = []
+        t0 = clock()
+        while pend or queue or active:
+            now = clock() - t0
+            while pend and pend[0].arrival <= now:
+                queue.append(pend.popleft())
+            for r in queue:
+                if r._mesh is None:
+                    self._prepare(r)
+            _, used, _ = L.gb_batch_info(self.batch)
+            n = admit_fifo([r.bytes for r in queue], self.budget - used)
+            for _ in range(n):
+                r = queue.popleft()
+                ticket = self._start(r)
+                r.t_admit = clock() - t0
+                active[ticket] = r
+            if not active:
+                if queue:
+                    # nothing running and the head still does not fit: it never will
+                    r = queue.popleft()
+                    r.rejected = True
+                    self._release(r)
+                    finished.append(r)
+                elif pend:
+                    sleep(max(0.0, pend[0].arrival - (clock() - t0)))
+                continue
+            L.gb_batch_run(self.batch, self.steps_per_launch)
+            if not self.classes:
+                self.classes = [L.gb_batch_class_info(self.batch, i)
+                                for i in range(L.gb_batch_class_count(self.batch))]
+            # build the meshes of requests that arrived meanwhile while the GPU steps
+            now = clock() - t0
+            while pend and pend[0].arrival <= now:
+                queue.append(pend.popleft())
+            for r in queue:
+                if r._mesh is None:
+                    self._prepare(r)
+            for ticket in L.gb_batch_poll(self.batch, len(active)):
+                r = active.pop(ticket)
+                r.t_done = clock() - t0
+                self._finish(r)
+                finished.append(r)
+        done = [r for r in finished if not r.rejected]
+        lat = [r.t_done - r.arrival for r in done]
+        work = sum(4.0 * r.dof * r.nsteps for r in done)
+        first = min((r.arrival for r in done), default=0.0)
+        last = max((r.t_done for r in done), default=0.0)
+        span = max(last - first, 1e-12)
+        return {"requests": len(requests), "completed": len(done),
+                "rejected": sum(r.rejected for r in finished),
+                "latency_s": latency_summary(lat),
+                "wait_s": latency_summary([r.t_admit - r.arrival for r in done]),
+                "makespan_s": span, "dof_stages": work, "gdof_stage_s": work / span / 1e9,
+                "classes": self.classes}
+
+    def close(self):
+        if self.batch:
+            L.gb_batch_destroy(self.batch)
+            self.batch = None
+            L.gb_ctx_destroy(self.setup_ctx)
+            L.gb_ctx_destroy(self.run_ctx)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serial_rate(req: Request, device: int = 0, stream: int = 0, steps: int = 20, warmup: int = 3) -> float:
+    """Seconds per step of the request solved alone (graph replay of the
+    single-mesh path), from `steps` timed steps after `warmup`."""
+    ctx = L.gb_ctx_create(device, stream)
+    c = req.case
+    mesh = L.gb_mesh_create(ctx, c.dim, c.N, c.vx, c.etov, c.period, c.face_tag)
+    try:
+        kind, p = motion_params(c.motion)
+        L.gb_set_motion(mesh, kind, p)
+        s = L.gb_solver_create(mesh, case_params(c, req.precision))
+        try:
+            L.gb_state_set(s, initial_state(c, mesh))
+            L.gb_sark_step_graph(s, c.dt, warmup)
+            L.gb_ctx_synchronize(ctx)
+            t0 = time.perf_counter()
+            L.gb_sark_step_graph(s, c.dt, steps)
+            L.gb_ctx_synchronize(ctx)
+            return (time.perf_counter() - t0) / steps
+        finally:
+            L.gb_solver_destroy(s)
+    finally:
+        L.gb_mesh_destroy(mesh)
+        L.gb_ctx_destroy(ctx)

@@ -1,0 +1,245 @@
+"""Batched and served forms (through the C ABI).
+
+Every request's result in a batch must equal, bit for bit, the same request
+solved alone with gb_sark_step: both run the same per-group code, the batch
+only changes which workgroup handles which group.  The alone path is checked
+against the oracle elsewhere; one batched FP64 request is also checked against
+the oracle directly here.
+"""
+import numpy as np
+import pytest
+
+from oracle import gbsystem as gb
+from oracle.mesh import Mesh
+from oracle.motion import Motion
+from oracle.rhs import Params
+from oracle.solver import Solver
+from workloads import make_case
+from workloads.configs import c5_case, c5_requests
+
+pytestmark = pytest.mark.gpu
+
+from paper_2607_00199_amd import _lib as L  # noqa: E402
+from paper_2607_00199_amd import serve as S  # noqa: E402
+from paper_2607_00199_amd.session import motion_params  # noqa: E402
+
+BIG = 1 << 40
+
+
+def _mix():
+    """(case, precision, nsteps): triangles of orders 2-4 in FP32 and FP64, a
+    walled O-grid with far field and sponge, and tetrahedra."""
+    return [
+        (make_case("C4", n_r=8, n_theta=16, N=2), L.GB_FP32, 7),
+        (make_case("C1", n=8, N=4), L.GB_FP32, 12),
+        (make_case("C3", n=3, N=2), L.GB_FP32, 5),
+        (make_case("C1", n=8, N=3), L.GB_FP64, 9),
+        (make_case("C1", n=6, N=4), L.GB_FP32, 4),
+    ]
+
+
+class _Req:
+    def __init__(self, ctx, case, prec):
+        self.case, self.prec = case, prec
+        self.mesh = L.gb_mesh_create(ctx, case.dim, case.N, case.vx, case.etov, case.period, case.face_tag)
+        kind, p = motion_params(case.motion)
+        L.gb_set_motion(self.mesh, kind, p)
+        self.K, self.Np, self.NF, _, _ = L.gb_mesh_sizes(self.mesh)
+        self.solver = L.gb_solver_create(self.mesh, S.case_params(case, prec))
+        self.q0 = S.initial_state(case, self.mesh)
+        L.gb_state_set(self.solver, self.q0)
+
+    def state(self):
+        return L.gb_state_get(self.solver, (self.K, self.NF, self.Np))
+
+    def close(self):
+        L.gb_solver_destroy(self.solver)
+        L.gb_mesh_destroy(self.mesh)
+
+
+def _alone(ctx, case, prec, nsteps):
+    r = _Req(ctx, case, prec)
+    L.gb_sark_step(r.solver, case.dt, nsteps)
+    out = r.state()
+    r.close()
+    return out
+
+
+def test_batch_alone_vs_mix_bitwise():
+    ctx = L.gb_ctx_create(0, 0)
+    mix = _mix()
+    ref = [_alone(ctx, c, p, n) for c, p, n in mix]
+    b = L.gb_batch_create(ctx, BIG)
+    reqs = [_Req(ctx, c, p) for c, p, _ in mix]
+    tickets = {}
+    # the first three join at once, the other two after two launches
+    for i in range(3):
+        tickets[L.gb_batch_add(b, reqs[i].solver, mix[i][0].dt, mix[i][2])] = i
+    L.gb_batch_run(b, 2)
+    assert L.gb_batch_poll(b) == []
+    L.gb_batch_run(b, 1)
+    for i in (3, 4):
+        tickets[L.gb_batch_add(b, reqs[i].solver, mix[i][0].dt, mix[i][2])] = i
+    done = []
+    for _ in range(20):
+        L.gb_batch_run(b, 3)
+        done += L.gb_batch_poll(b)
+        if len(done) == len(mix):
+            break
+    assert sorted(tickets[t] for t in done) == list(range(len(mix)))
+    assert L.gb_batch_info(b)[0] == 0
+    for i, r in enumerate(reqs):
+        q, t, step = r.state()
+        qa, ta, stepa = ref[i]
+        assert step == stepa == mix[i][2], i
+        assert t == ta, i
+        assert np.array_equal(q, qa), (i, np.abs(q - qa).max())
+    L.gb_batch_destroy(b)
+    for r in reqs:
+        r.close()
+    L.gb_ctx_destroy(ctx)
+
+
+def test_batch_fp64_request_matches_oracle():
+    case = make_case("C1", n=8, N=3)
+    ctx = L.gb_ctx_create(0, 0)
+    r = _Req(ctx, case, L.GB_FP64)
+    other = _Req(ctx, make_case("C1", n=6, N=2), L.GB_FP64)
+    b = L.gb_batch_create(ctx, BIG)
+    L.gb_batch_add(b, r.solver, case.dt, 6)
+    L.gb_batch_add(b, other.solver, case.dt, 3)
+    L.gb_batch_run(b, 6)
+    assert len(L.gb_batch_poll(b)) == 2
+    q, t, step = r.state()
+    mesh = Mesh(case.dim, case.N, case.vx, case.etov, case.period, face_tag=case.face_tag)
+    mot = dict(case.motion)
+    o = Solver(mesh, Params(c=case.c, tau=case.tau), Motion(mot.pop("kind"), **mot))
+    X = o.node_coords()
+    rho, u = case.macroscopic(X)
+    o.set_state(gb.equilibrium(case.dim, rho, u, case.c).transpose(1, 0, 2).copy())
+    o.run(case.dt, 6)
+    scale = np.abs(o.q).max(axis=(0, 2))
+    assert step == 6
+    assert (np.abs(q - o.q).max(axis=(0, 2)) <= 1e-12 * np.maximum(scale, 1e-3)).all()
+    L.gb_batch_destroy(b)
+    r.close()
+    other.close()
+    L.gb_ctx_destroy(ctx)
+
+
+def test_batch_admission_budget_and_tuning():
+    ctx = L.gb_ctx_create(0, 0)
+    c1, c2 = make_case("C1", n=8, N=4), make_case("C1", n=8, N=2)
+    ref2 = _alone(ctx, c2, L.GB_FP32, 4)
+    r1, r2 = _Req(ctx, c1, L.GB_FP32), _Req(ctx, c2, L.GB_FP32)
+    need1 = L.gb_solver_footprint(r1.mesh, S.case_params(c1, L.GB_FP32)) + L.gb_mesh_footprint(r1.mesh)
+    b = L.gb_batch_create(ctx, need1 + 1024)
+    L.gb_batch_add(b, r1.solver, c1.dt, 3)
+    with pytest.raises(L.GbError) as ei:
+        L.gb_batch_add(b, r2.solver, c2.dt, 4)
+    assert ei.value.status == L.GB_ERR_BUSY
+    active, used, budget = L.gb_batch_info(b)
+    assert active == 1 and used == need1 and budget == need1 + 1024
+    L.gb_batch_run(b, 3)
+    assert len(L.gb_batch_poll(b)) == 1
+    assert L.gb_batch_info(b)[1] == 0
+    # tuned grid is one of the candidates
+    info = L.gb_batch_class_info(b, 0) if L.gb_batch_class_count(b) else None
+    assert info is not None and info["members"] == 1
+    ncu = info["grid"]
+    assert any(ncu % m == 0 for m in (1, 2, 4, 8, 16))
+    # now the second fits
+    need2 = L.gb_solver_footprint(r2.mesh, S.case_params(c2, L.GB_FP32)) + L.gb_mesh_footprint(r2.mesh)
+    if need2 <= need1 + 1024:
+        L.gb_batch_add(b, r2.solver, c2.dt, 4)
+        L.gb_batch_run(b, 4)
+        assert len(L.gb_batch_poll(b)) == 1
+        q, t, step = r2.state()
+        assert step == 4 and np.array_equal(q, ref2[0])
+    L.gb_batch_destroy(b)
+    r1.close()
+    r2.close()
+    L.gb_ctx_destroy(ctx)
+
+
+def test_batch_errors():
+    ctx = L.gb_ctx_create(0, 0)
+    c = make_case("C1", n=4, N=2)
+    r = _Req(ctx, c, L.GB_FP32)
+    b = L.gb_batch_create(ctx, BIG)
+    with pytest.raises(L.GbError) as ei:
+        L.gb_batch_add(b, r.solver, c.dt, 0)
+    assert ei.value.status == L.GB_ERR_ARG
+    L.gb_batch_add(b, r.solver, c.dt, 1)
+    with pytest.raises(L.GbError) as ei:
+        L.gb_batch_add(b, r.solver, c.dt, 1)
+    assert ei.value.status == L.GB_ERR_STATE
+    L.gb_batch_run(b, 0)
+    L.gb_batch_run(b, 2)
+    assert len(L.gb_batch_poll(b)) == 1
+    assert r.state()[2] == 1      # stopped at its target although two steps ran
+    L.gb_batch_destroy(b)
+    r.close()
+    L.gb_ctx_destroy(ctx)
+
+
+def test_served_small_mix_matches_alone():
+    """Served loop on a small request mix (orders 2-5, arrivals 5 ms apart):
+    every request completes, and its final state equals the request solved
+    alone."""
+    import torch
+    specs = c5_requests(n=6, seed=3, mean_gap=0.005, nsteps=6, sizes=(4, 6), orders=(2, 3, 4, 5))
+    reqs = [S.Request(index=s["index"], arrival=s["arrival"], case=c5_case(s), nsteps=s["nsteps"],
+                      keep_state=True) for s in specs]
+    s_run, s_setup = torch.cuda.Stream(), torch.cuda.Stream()
+    srv = S.Server(BIG, run_stream=s_run.cuda_stream, setup_stream=s_setup.cuda_stream, steps_per_launch=2)
+    stats = srv.serve(reqs)
+    srv.close()
+    assert stats["completed"] == 6 and stats["rejected"] == 0
+    assert stats["latency_s"]["p50"] > 0 and stats["latency_s"]["max"] >= stats["latency_s"]["p99"]
+    ctx = L.gb_ctx_create(0, 0)
+    for r in reqs:
+        q, t, step = _alone(ctx, r.case, r.precision, r.nsteps)
+        assert r.steps_done == step == r.nsteps
+        assert np.array_equal(r.state, q), r.index
+    L.gb_ctx_destroy(ctx)
+
+
+def test_served_admission_under_small_budget():
+    """A budget that holds about two of the requests: all complete, in
+    arrival order of admission, none rejected."""
+    import torch
+    specs = c5_requests(n=5, seed=4, mean_gap=0.002, nsteps=4, sizes=(6,), orders=(3,))
+    reqs = [S.Request(index=s["index"], arrival=s["arrival"], case=c5_case(s), nsteps=s["nsteps"])
+            for s in specs]
+    probe = L.gb_ctx_create(0, 0)
+    c = reqs[0].case
+    m = L.gb_mesh_create(probe, c.dim, c.N, c.vx, c.etov, c.period, c.face_tag)
+    one = L.gb_solver_footprint(m, S.case_params(c, L.GB_FP32)) + L.gb_mesh_footprint(m)
+    L.gb_mesh_destroy(m)
+    L.gb_ctx_destroy(probe)
+    s_run, s_setup = torch.cuda.Stream(), torch.cuda.Stream()
+    srv = S.Server(2 * one + one // 2, run_stream=s_run.cuda_stream, setup_stream=s_setup.cuda_stream,
+                   steps_per_launch=1)
+    stats = srv.serve(reqs)
+    srv.close()
+    assert stats["completed"] == 5 and stats["rejected"] == 0
+    admits = [r.t_admit for r in sorted(reqs, key=lambda r: r.arrival)]
+    assert admits == sorted(admits)
+    assert all(r.steps_done == 4 for r in reqs)
+
+
+def test_batch_refuses_shapes_it_is_not_built_for():
+    """The batched kernel is built only for shapes whose kernel needs no
+    scratch memory; the others are refused at admission (no launch)."""
+    ctx = L.gb_ctx_create(0, 0)
+    c = make_case("C1", n=4, N=5)
+    r = _Req(ctx, c, L.GB_FP64)
+    b = L.gb_batch_create(ctx, BIG)
+    with pytest.raises(L.GbError) as ei:
+        L.gb_batch_add(b, r.solver, c.dt, 1)
+    assert ei.value.status == L.GB_ERR_UNSUPPORTED
+    assert L.gb_batch_info(b)[0] == 0
+    L.gb_batch_destroy(b)
+    r.close()
+    L.gb_ctx_destroy(ctx)

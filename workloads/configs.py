@@ -145,3 +145,32 @@ CASES = {
                nsteps=5000, init="uniform", u=(0.1, 0.0),
                sponge=(0.5, 0.0, 16.0, 20.0, 2.0)),
 }
+
+
+def c5_requests(n: int = 64, seed: int = 1, mean_gap: float = 0.05, nsteps: int = 1000,
+                sizes=(64, 128, 192, 256), orders=(2, 3, 4, 5)) -> list:
+    """The served-request mix: n plunging-airfoil requests with exponential
+    inter-arrival times (Poisson arrivals, mean gap in seconds), each with
+    its own O-grid size (n_r radial layers, 2 n_r points around the body,
+    K = 4 n_r^2 triangles), order, plunge amplitude h0 and frequency f, and
+    Reynolds number; Mach 0.1, nsteps steps.  Drawn from
+    numpy.random.default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(mean_gap, size=n)
+    arrival = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n):
+        n_r = int(rng.choice(sizes))
+        out.append(dict(index=i, arrival=float(arrival[i]), n_r=n_r, n_theta=2 * n_r, N=int(rng.choice(orders)),
+                        h0=float(rng.uniform(0.05, 0.2)), f=float(rng.uniform(0.25, 1.0)),
+                        Re=float(rng.uniform(1e3, 1e4)), nsteps=nsteps))
+    return out
+
+
+def c5_case(req: dict) -> Case:
+    """Case of one served request (the plunging-airfoil workload at the
+    request's size, order and parameters)."""
+    motion = dict(CASES["C4"]["motion"])
+    motion.update(h0=req["h0"], omega=2 * math.pi * req["f"])
+    return make_case("C4", n_r=req["n_r"], n_theta=req["n_theta"], N=req["N"], Re=req["Re"],
+                     motion=motion, nsteps=req["nsteps"])

@@ -116,13 +116,12 @@ def ogrid_airfoil(n_r: int, n_theta: int, radius: float = 20.0, thickness: float
     g = 0.5 * (lo_g + hi_g)
     s = (g ** np.arange(n_r + 1) - 1) / (g**n_r - 1)
     vx = (inner[None, :, :] + s[:, None, None] * (outer - inner)[None, :, :]).reshape(-1, 2)
-    vid = lambda j, k: k * n_theta + (j % n_theta)
-    tris, tags = [], []
-    for k in range(n_r):
-        for j in range(n_theta):
-            a, b, c, d = vid(j, k), vid(j + 1, k), vid(j + 1, k + 1), vid(j, k + 1)
-            tris += [(a, b, c), (a, c, d)]
-    etov = _orient(vx, np.array(tris, np.int64))
+    k, j = np.meshgrid(np.arange(n_r, dtype=np.int64), np.arange(n_theta, dtype=np.int64), indexing="ij")
+    a, b = k * n_theta + j, k * n_theta + (j + 1) % n_theta
+    c, d = (k + 1) * n_theta + (j + 1) % n_theta, (k + 1) * n_theta + j
+    # quad (k, j) -> triangles (a, b, c), (a, c, d), quads in (k, j) order
+    tris = np.stack([np.stack([a, b, c], -1), np.stack([a, c, d], -1)], axis=2).reshape(-1, 3)
+    etov = _orient(vx, tris)
     # face tags: a face on the body (both vertices in layer 0) is a wall, on the
     # outer circle (both in layer n_r) far field
     layer = np.arange(vx.shape[0]) // n_theta
