@@ -51,16 +51,21 @@ def run_gpu(precision_name: str, steps: int, warmup: int, n: int, graph: bool = 
 
     prec = L.GB_FP32 if precision_name == "f32" else L.GB_FP64
     case = make_case("C2", n=n)
-    stream = torch.cuda.current_stream().cuda_stream
-    s = Session(case, precision=prec, device=0, stream=stream)
+
+    def sync(sess):
+        # the library's own HIP runtime is not torch's: wait on both
+        L.gb_ctx_synchronize(sess.ctx)
+        torch.cuda.synchronize()
+
+    s = Session(case, precision=prec, device=0, stream=0)
     q0 = s.initial_state()
     s.set_state(q0)
     s.step(case.dt, warmup)
-    torch.cuda.synchronize()
+    sync(s)
     L.gb_solver_time_stages(s.solver, True)
     t0 = time.perf_counter()
     s.step(case.dt, steps)
-    torch.cuda.synchronize()
+    sync(s)
     el = time.perf_counter() - t0
     avg_ms, launches = L.gb_solver_stage_time(s.solver)
     by_kind = L.gb_solver_stage_time_by_kind(s.solver)
@@ -69,13 +74,13 @@ def run_gpu(precision_name: str, steps: int, warmup: int, n: int, graph: bool = 
     # graph replay of the same step, timed separately
     gel = float("nan")
     if graph:
-        s2 = Session(case, precision=prec, device=0, stream=stream)
+        s2 = Session(case, precision=prec, device=0, stream=0)
         s2.set_state(q0)
         s2.step(case.dt, warmup, graph=True)
-        torch.cuda.synchronize()
+        sync(s2)
         g0 = time.perf_counter()
         s2.step(case.dt, steps, graph=True)
-        torch.cuda.synchronize()
+        sync(s2)
         gel = time.perf_counter() - g0
         s2.close()
     K, Np, NF = s.K, s.Np, s.NF
@@ -127,8 +132,6 @@ def run_served(args) -> dict:
     """The served form on the request mix: Poisson arrivals of plunging-airfoil
     requests of mixed size and order, continuous batching under an HBM budget;
     then every request timed alone (graph replay) for the serial reference."""
-    import torch
-
     from paper_2607_00199_amd import serve as S
     from workloads.configs import c5_case, c5_requests
 
@@ -137,15 +140,13 @@ def run_served(args) -> dict:
     reqs = [S.Request(index=q["index"], arrival=q["arrival"], case=c5_case(q), nsteps=q["nsteps"]) for q in specs]
     print(f"served: {len(reqs)} request meshes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     budget = int(args.budget_gib * (1 << 30)) if args.budget_gib > 0 else (1 << 50)
-    s_run, s_setup = torch.cuda.Stream(), torch.cuda.Stream()
-    srv = S.Server(budget, run_stream=s_run.cuda_stream, setup_stream=s_setup.cuda_stream,
-                   steps_per_launch=args.steps_per_launch)
+    srv = S.Server(budget, steps_per_launch=args.steps_per_launch)
     stats = srv.serve(reqs)
     srv.close()
     print(f"served: {stats['completed']} done in {stats['makespan_s']:.1f} s", file=sys.stderr, flush=True)
     serial_s = 0.0
     for r in reqs:
-        serial_s += S.serial_rate(r, stream=s_run.cuda_stream, steps=args.serial_steps) * r.nsteps
+        serial_s += S.serial_rate(r, steps=args.serial_steps) * r.nsteps
     work = stats["dof_stages"]
     return {"stats": stats, "serial_seconds": serial_s, "serial_gdof_stage_s": work / serial_s / 1e9,
             "budget_bytes": budget, "requests": [

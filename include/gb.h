@@ -128,6 +128,15 @@ void gb_ctx_destroy(gb_ctx *ctx);
 /* Block until all work the context enqueued has finished. */
 gb_status gb_ctx_synchronize(gb_ctx *ctx);
 
+/* A non-blocking HIP stream (default priority) of this library's HIP
+ * runtime, for gb_ctx_create.  A process can hold more than one HIP runtime
+ * (another framework may bundle its own); stream handles are not
+ * interchangeable between runtimes, so pass either NULL (the null stream) or
+ * a stream from this call. */
+gb_status gb_stream_create(int device, void **stream);
+void gb_stream_destroy(void *stream);
+
+
 /* Build a mesh (Section 3: K non-overlapping, straight-sided, positively
  * oriented simplices with a fixed topology).
  *   dim      2 or 3;  N  polynomial order (2D: 1..5, 3D: 1..3)

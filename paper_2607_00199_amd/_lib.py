@@ -54,6 +54,8 @@ SIGNATURES = {
     "gb_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "gb_ctx_destroy": (None, [_P]),
     "gb_ctx_synchronize": (C.c_int, [_P]),
+    "gb_stream_create": (C.c_int, [C.c_int, C.POINTER(_P)]),
+    "gb_stream_destroy": (None, [_P]),
     "gb_mesh_create": (C.c_int, [_P, C.c_int, C.c_int, _i64, _dp, _i64, C.POINTER(C.c_int32), _dp,
                                  C.POINTER(C.c_int8), C.POINTER(_P)]),
     "gb_mesh_destroy": (None, [_P]),
@@ -136,6 +138,18 @@ def gb_ctx_destroy(ctx):
 
 def gb_ctx_synchronize(ctx):
     _check(load().gb_ctx_synchronize(ctx))
+
+
+def gb_stream_create(device: int = 0) -> int:
+    """A non-blocking stream of this library's HIP runtime (an integer
+    handle for gb_ctx_create)."""
+    out = _P()
+    _check(load().gb_stream_create(device, C.byref(out)))
+    return out.value or 0
+
+
+def gb_stream_destroy(stream: int):
+    load().gb_stream_destroy(_P(stream or None))
 
 
 def gb_mesh_create(ctx, dim: int, N: int, vx, etov, period=None, face_tag=None):

@@ -122,7 +122,7 @@ hipError_t launch_stage_batch(const BatchLaunch &L, int kind, hipStream_t st) {
     const K0 fns[5] = {&stage_batch_kernel<DIM, N, T, 0>, &stage_batch_kernel<DIM, N, T, 1>,
                        &stage_batch_kernel<DIM, N, T, 2>, &stage_batch_kernel<DIM, N, T, 3>,
                        &stage_batch_kernel<DIM, N, T, 4>};
-    hipLaunchKernelGGL(fns[kind < 4 ? kind : 4], dim3(grid), dim3(64 * kWaves), L.lds, st, b);
+    hipLaunchKernelGGL(fns[kind < 4 ? kind : 4], dim3(grid), dim3(64 * kWaves), L.lds, st, b, b.ent);
     return hipGetLastError();
 }
 

@@ -663,6 +663,23 @@ gb_status gb_ctx_create(int device, void *stream, gb_ctx **out) {
 
 void gb_ctx_destroy(gb_ctx *ctx) { delete ctx; }
 
+gb_status gb_stream_create(int device, void **stream) {
+    if (!stream) return fail(GB_ERR_ARG, "stream is NULL");
+    *stream = nullptr;
+    int n = 0;
+    GB_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(GB_ERR_ARG, "device index out of range");
+    GB_HIP(hipSetDevice(device));
+    hipStream_t st;
+    GB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    *stream = st;
+    return GB_OK;
+}
+
+void gb_stream_destroy(void *stream) {
+    if (stream) (void)hipStreamDestroy(static_cast<hipStream_t>(stream));
+}
+
 gb_status gb_ctx_synchronize(gb_ctx *ctx) {
     if (!ctx) return fail(GB_ERR_ARG, "ctx is NULL");
     GB_HIP(hipStreamSynchronize(ctx->stream));

@@ -265,7 +265,7 @@ __host__ __device__ constexpr bool batch_enabled() {
 
 template <int DIM, int N, typename T, int STAGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<DIM, N>(sizeof(T)))))
-stage_batch_kernel(BatchArgs<T> b) {
+stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
     using S = Shape<DIM, N>;
     using MS = MShape<DIM, N>;
     using O = MOps<DIM, N>;
@@ -303,7 +303,7 @@ stage_batch_kernel(BatchArgs<T> b) {
     for (int gi = g_begin + wave; gi < g_end; gi += nwave) {
         const int gt = __builtin_amdgcn_readfirstlane(gi);
         const int r = __builtin_amdgcn_readfirstlane(table_search(s_gb, b.nreq, gt));
-        const BatchEntry<T> &E = b.ent[r];
+        const BatchEntry<T> &E = ent[r];
         if (E.clock[1] >= E.target) continue;
         KArgs<T> a;
         a.K = E.K;

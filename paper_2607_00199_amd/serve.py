@@ -101,13 +101,13 @@ def initial_state(case, mesh) -> np.ndarray:
 class Server:
     """One batch on one device, with a separate context (stream) for request
     setup so that building and uploading a new request does not wait for the
-    batch's queued steps.  Pass non-blocking streams (e.g. torch.cuda.Stream
-    handles) for both."""
+    batch's queued steps.  Both streams are non-blocking streams of the
+    library's own HIP runtime."""
 
-    def __init__(self, budget_bytes: int, device: int = 0, run_stream: int = 0, setup_stream: int = 0,
-                 steps_per_launch: int = 5, autotune: bool = True):
-        self.run_ctx = L.gb_ctx_create(device, run_stream)
-        self.setup_ctx = L.gb_ctx_create(device, setup_stream)
+    def __init__(self, budget_bytes: int, device: int = 0, steps_per_launch: int = 5, autotune: bool = True):
+        self.streams = [L.gb_stream_create(device), L.gb_stream_create(device)]
+        self.run_ctx = L.gb_ctx_create(device, self.streams[0])
+        self.setup_ctx = L.gb_ctx_create(device, self.streams[1])
         self.batch = L.gb_batch_create(self.run_ctx, budget_bytes)
         L.gb_batch_set_autotune(self.batch, autotune)
         self.budget = int(budget_bytes)
@@ -212,6 +212,8 @@ class Server:
             self.batch = None
             L.gb_ctx_destroy(self.setup_ctx)
             L.gb_ctx_destroy(self.run_ctx)
+            for st in self.streams:
+                L.gb_stream_destroy(st)
 
     def __del__(self):
         try:
@@ -220,10 +222,10 @@ class Server:
             pass
 
 
-def serial_rate(req: Request, device: int = 0, stream: int = 0, steps: int = 20, warmup: int = 3) -> float:
+def serial_rate(req: Request, device: int = 0, steps: int = 20, warmup: int = 3) -> float:
     """Seconds per step of the request solved alone (graph replay of the
     single-mesh path), from `steps` timed steps after `warmup`."""
-    ctx = L.gb_ctx_create(device, stream)
+    ctx = L.gb_ctx_create(device, 0)
     c = req.case
     mesh = L.gb_mesh_create(ctx, c.dim, c.N, c.vx, c.etov, c.period, c.face_tag)
     try:

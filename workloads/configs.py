@@ -138,9 +138,10 @@ CASES = {
     "C3": dict(mesh="kuhn", n=48, dim=3, N=3, c=1.0, u0=0.1, Re=1600.0, Lref=1.0,
                motion={"kind": "triple_product_3d", "A": 0.03, "T": 20.0, "L": 2 * math.pi},
                nsteps=500, init="tgv3d"),
-    # plunging NACA 0012 O-grid, 256 x 512 quads -> 262144 triangles, N=4
+    # plunging NACA 0012 O-grid, 256 x 512 quads -> 262144 triangles, N=4;
+    # the plunge frequency is in convective time (t U / chord): omega = 2 pi f U
     "C4": dict(mesh="ogrid", n_r=256, n_theta=512, dim=2, N=4, c=1.0, u0=0.1, Re=1e4, Lref=1.0,
-               motion={"kind": "plunge_blend_2d", "h0": 0.1, "omega": 2 * math.pi * 0.5,
+               motion={"kind": "plunge_blend_2d", "h0": 0.1, "omega": 2 * math.pi * 0.5 * 0.1,
                        "r_in": 1.5, "r_out": 16.0, "center": (0.5, 0.0)},
                nsteps=5000, init="uniform", u=(0.1, 0.0),
                sponge=(0.5, 0.0, 16.0, 20.0, 2.0)),
@@ -171,6 +172,7 @@ def c5_case(req: dict) -> Case:
     """Case of one served request (the plunging-airfoil workload at the
     request's size, order and parameters)."""
     motion = dict(CASES["C4"]["motion"])
-    motion.update(h0=req["h0"], omega=2 * math.pi * req["f"])
+    # frequency f in convective time units (chord / U), U = 0.1
+    motion.update(h0=req["h0"], omega=2 * math.pi * req["f"] * CASES["C4"]["u0"])
     return make_case("C4", n_r=req["n_r"], n_theta=req["n_theta"], N=req["N"], Re=req["Re"],
                      motion=motion, nsteps=req["nsteps"])
