@@ -26,7 +26,7 @@ def test_c5_case_sizes():
     q = dict(index=0, arrival=0.0, n_r=8, n_theta=16, N=3, h0=0.1, f=0.5, Re=2000.0, nsteps=10)
     c = c5_case(q)
     assert c.K == 4 * 8 * 8 and c.N == 3 and c.nsteps == 10
-    assert c.motion["h0"] == 0.1 and abs(c.motion["omega"] - math.pi) < 1e-15
+    assert c.motion["h0"] == 0.1 and abs(c.motion["omega"] - math.pi * 0.1) < 1e-15   # 2 pi f U, U = 0.1
     assert abs(c.tau - 0.1 / 2000.0) < 1e-18
     assert (c.face_tag == 1).sum() == 16 and (c.face_tag == 2).sum() == 16
 
