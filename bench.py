@@ -30,6 +30,29 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per stage launch of the FP32 2D N=4 stage kernel at 131072
+# triangles, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by kernels of
+# known size (profiles/stage_kernel_c2_256_n4_mfma.md).  Reported only while
+# the kernel sources still hash to the digest they were measured with.
+MEASURED_TRAFFIC = {
+    "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
+                "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp"],
+    "sha256": "253916ab1690665a453fd1f2a3ee65198f66214c047767b1242dd988fdeb1297",
+    "K": 131072,
+    "bytes_per_launch": 216474 * 1024,
+}
+
+
+def measured_traffic(K: int):
+    import hashlib
+    h = hashlib.sha256()
+    for f in MEASURED_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != MEASURED_TRAFFIC["sha256"] or K != MEASURED_TRAFFIC["K"]:
+        return None
+    return MEASURED_TRAFFIC["bytes_per_launch"]
+
 
 def algorithmic_bytes_per_launch(K: int, Np: int, NF: int, dim: int, elem_bytes: int) -> float:
     """Bytes the stage kernel must move per launch: 15 state passes per
@@ -219,7 +242,7 @@ def main():
     K, Np, NF = r32["K"], r32["Np"], r32["NF"]
     bytes_launch = algorithmic_bytes_per_launch(K, Np, NF, 2, 4)
     achieved = bytes_launch / (r32["stage_avg_ms"] * 1e-3) / 1e9
-    traffic = None
+    traffic = measured_traffic(K)
     out = {
         "metric": "GDOF-stage/s (FP32 perturbation storage; FP64 beside it)",
         "value": round(r32["gdof_stage_s"], 3),
