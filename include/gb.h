@@ -227,10 +227,11 @@ gb_status gb_solver_stage_time_by_kind(gb_solver *solver, double *avg_ms4);
 /* ------------------------------------------------------------------------
  * Batched form: many solvers (meshes of any size, orders and precisions on
  * one device) advanced together.  Each step of the batch is one captured HIP
- * graph: a vertex-motion launch per dimension, then for each of the four
- * SARK-4 stages one stage launch per class (same dimension, order, precision
- * and cubature rule) over the concatenated element groups of its members,
- * then the end-of-step vertex update.  The kernels read a device request
+ * graph: a vertex-motion launch per dimension; the four SARK-4 stages of
+ * each large member in turn; for each of the four stages one launch per
+ * class (same dimension, order, precision and cubature rule) over the
+ * concatenated element groups of its smaller members; then the end-of-step
+ * vertex update.  The kernels read a device request
  * table (buffers, group offsets, constants, clock and target step of every
  * member); a member whose step counter has reached its target is skipped, so
  * members finish at different steps while the graph keeps replaying.  The
@@ -272,10 +273,14 @@ gb_status gb_batch_info(const gb_batch *batch, int *active, size_t *used_bytes, 
 /* Enable (default) or disable the launch-grid tuning of new classes. */
 gb_status gb_batch_set_autotune(gb_batch *batch, int enable);
 
-/* Classes of the current table (valid after gb_batch_run): info[6] =
- * {dim, N, precision, members, element groups, launch grid}. */
+/* Launch classes of the current table (valid after gb_batch_run): info[7] =
+ * {dim, N, precision, members, element groups, launch grid, solo}; solo = 1
+ * for a member large enough (>= 2048 groups of 16 elements) to be stepped on
+ * its own, its four stages back to back so its state stays in the
+ * last-level cache; the smaller members of a class share one launch per
+ * stage. */
 gb_status gb_batch_class_count(const gb_batch *batch, int *n);
-gb_status gb_batch_class_info(const gb_batch *batch, int i, int64_t *info6);
+gb_status gb_batch_class_info(const gb_batch *batch, int i, int64_t *info7);
 
 #ifdef __cplusplus
 }

@@ -330,6 +330,6 @@ def gb_batch_class_count(batch) -> int:
 
 
 def gb_batch_class_info(batch, i: int) -> dict:
-    out = (_i64 * 6)()
+    out = (_i64 * 7)()
     _check(load().gb_batch_class_info(batch, i, out))
-    return dict(zip(("dim", "N", "precision", "members", "groups", "grid"), (int(v) for v in out)))
+    return dict(zip(("dim", "N", "precision", "members", "groups", "grid", "solo"), (int(v) for v in out)))

@@ -223,17 +223,17 @@ gbd::BatchEntry<T> make_entry(const gb_solver *s, double target) {
     gbd::BatchEntry<T> e{};
     e.K = m->K;
     e.nv = m->nv;
-    e.etov = m->d_etov.as<int32_t>();
-    e.vstage = s->vstage.as<double>();
-    e.wstage = s->wstage.as<double>();
-    e.vmapP = m->d_vmapP.as<int32_t>();
-    e.Q = s->Q.as<T>();
-    e.A = s->A.as<T>();
-    e.B = s->B.as<T>();
-    e.G = s->G.as<T>();
-    e.clock = s->clock.as<double>();
-    e.kc = s->kconst.as<gbd::KConst<T>>();
-    e.err = s->err.as<int>();
+    e.etov = (GB_GLOBAL const int32_t *)m->d_etov.as<int32_t>();
+    e.vstage = (GB_GLOBAL const double *)s->vstage.as<double>();
+    e.wstage = (GB_GLOBAL const double *)s->wstage.as<double>();
+    e.vmapP = (GB_GLOBAL const int32_t *)m->d_vmapP.as<int32_t>();
+    e.Q = (GB_GLOBAL T *)s->Q.as<T>();
+    e.A = (GB_GLOBAL T *)s->A.as<T>();
+    e.B = (GB_GLOBAL T *)s->B.as<T>();
+    e.G = (GB_GLOBAL T *)s->G.as<T>();
+    e.clock = (GB_GLOBAL const double *)s->clock.as<double>();
+    e.kc = (GB_GLOBAL const gbd::KConst<T> *)s->kconst.as<gbd::KConst<T>>();
+    e.err = (GB_GLOBAL int *)s->err.as<int>();
     e.target = target;
     return e;
 }
@@ -399,6 +399,7 @@ struct gb_batch {
     std::vector<Member> members;
     struct Class {
         int dim = 2, N = 1, prec = 0, Nc = 0;
+        bool solo = false;          // one large member stepped on its own
         std::vector<int> idx;       // member indices
         gbd::ShapeEntry shape{};
         DevBuf ent, gbeg;
@@ -413,7 +414,7 @@ struct gb_batch {
     DevBuf mot[2];                  // gbd::MotionEntry tables, 2D and 3D
     int nmot[2] = {0, 0};
     int64_t vtot[2] = {0, 0};
-    std::map<std::array<int, 4>, int> tuned;   // (dim, N, precision, Nc) -> grid
+    std::map<std::array<int, 5>, int> tuned;   // (dim, N, precision, Nc, solo) -> grid
     hipGraphExec_t graph = nullptr;
     bool dirty = true;
     ~gb_batch() {
@@ -422,6 +423,10 @@ struct gb_batch {
 };
 
 namespace {
+
+// Element groups from which a member is stepped on its own (2048 groups of
+// 16 elements give one group to each wavefront of two workgroups per CU).
+constexpr int64_t kSoloGroups = 2048;
 
 size_t mesh_bytes(const gb_mesh *m) { return m->d_etov.bytes + m->d_X.bytes + m->d_x.bytes + m->d_vmapP.bytes; }
 
@@ -531,13 +536,19 @@ gb_status batch_rebuild(gb_batch *b) {
         GB_HIP(hipGraphExecDestroy(b->graph));
         b->graph = nullptr;
     }
+    // Members with enough element groups to fill the GPU on their own are
+    // stepped one after another, each with its four stages back to back, so
+    // each one's state arrays stay in the last-level cache across its stages;
+    // the smaller members of a class share one launch per stage.
     b->classes.clear();
     for (size_t i = 0; i < b->members.size(); ++i) {
         const gb_solver *s = b->members[i].s;
         const int dim = s->mesh->dim, N = s->mesh->N, prec = s->prm.precision, Nc = s->ref.Nc;
+        const bool solo = (s->mesh->K + 15) / 16 >= kSoloGroups;
         gb_batch::Class *c = nullptr;
-        for (auto &cc : b->classes)
-            if (cc.dim == dim && cc.N == N && cc.prec == prec && cc.Nc == Nc) c = &cc;
+        if (!solo)
+            for (auto &cc : b->classes)
+                if (!cc.solo && cc.dim == dim && cc.N == N && cc.prec == prec && cc.Nc == Nc) c = &cc;
         if (!c) {
             b->classes.emplace_back();
             c = &b->classes.back();
@@ -545,6 +556,7 @@ gb_status batch_rebuild(gb_batch *b) {
             c->N = N;
             c->prec = prec;
             c->Nc = Nc;
+            c->solo = solo;
         }
         c->idx.push_back(int(i));
     }
@@ -562,8 +574,8 @@ gb_status batch_rebuild(gb_batch *b) {
         const gb_solver *s0 = b->members[size_t(c.idx[0])].s;
         c.ops = s0->ops.p;
         c.fmask = s0->fmask.as<int32_t>();
-        auto it = b->tuned.find({c.dim, c.N, c.prec, c.Nc});
-        c.grid = it != b->tuned.end() ? it->second : b->ctx->num_cu * 8;
+        auto it = b->tuned.find({c.dim, c.N, c.prec, c.Nc, int(c.solo)});
+        c.grid = it != b->tuned.end() ? it->second : b->ctx->num_cu * 2;
     }
     for (int di = 0; di < 2; ++di) {
         std::vector<gbd::MotionEntry> E;
@@ -596,7 +608,7 @@ gb_status batch_rebuild(gb_batch *b) {
     }
     if (b->autotune)
         for (auto &c : b->classes) {
-            const std::array<int, 4> key{c.dim, c.N, c.prec, c.Nc};
+            const std::array<int, 5> key{c.dim, c.N, c.prec, c.Nc, int(c.solo)};
             if (b->tuned.count(key)) continue;
             const gb_status r = tune_class(b, c);
             if (r != GB_OK) return r;
@@ -614,9 +626,12 @@ gb_status batch_rebuild(gb_batch *b) {
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
         for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, di, false, cap);
+        for (auto &c : b->classes)
+            for (int kind = 0; kind < 4 && le == hipSuccess && c.solo; ++kind)
+                le = c.shape.batch_stage(class_launch(c, c.grid), kind, cap);
         for (int kind = 0; kind < 4 && le == hipSuccess; ++kind)
             for (auto &c : b->classes)
-                if (le == hipSuccess) le = c.shape.batch_stage(class_launch(c, c.grid), kind, cap);
+                if (le == hipSuccess && !c.solo) le = c.shape.batch_stage(class_launch(c, c.grid), kind, cap);
         for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, di, true, cap);
         e = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess && le != hipSuccess) {
@@ -868,7 +883,10 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     s->epb = 16;
     s->lds = need;
     s->kconst_host.assign(std::max(sizeof(gbd::KConst<double>), sizeof(gbd::KConst<float>)), 0);
-    s->grid = m->ctx->num_cu * 8;
+    // two workgroups per CU, each persistent over a contiguous range of
+    // element groups (the operator fragments are staged in LDS once per
+    // workgroup); measured faster than one workgroup per group
+    s->grid = m->ctx->num_cu * 2;
     GB_HIP(hipSetDevice(m->ctx->device));
     const size_t n = size_t((m->K + 15) / 16 * 16) * s->NF * Np;   // padded to whole groups of 16
     if (s->Q.alloc(n * s->elem_bytes) != hipSuccess || s->A.alloc(n * s->elem_bytes) != hipSuccess ||
@@ -1246,6 +1264,7 @@ gb_status gb_batch_class_info(const gb_batch *b, int i, int64_t *info) {
     info[3] = c.nreq;
     info[4] = c.total;
     info[5] = c.grid;
+    info[6] = c.solo ? 1 : 0;
     return GB_OK;
 }
 

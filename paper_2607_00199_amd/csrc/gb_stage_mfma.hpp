@@ -221,17 +221,22 @@ stage_mfma_kernel(KArgs<T> a) {
 // Request table of the batched stage kernel: one entry per mesh of a class
 // (same dimension, order, precision and cubature rule, so one set of operator
 // fragments serves every entry).
+// Pointers in the table are declared in the global address space (they come
+// from hipMalloc), so the kernel reaches the buffers with global rather than
+// flat memory instructions.
+#define GB_GLOBAL __attribute__((address_space(1)))
+
 template <typename T>
 struct BatchEntry {
     int64_t K, nv;
-    const int32_t *etov;
-    const double *vstage, *wstage;   // [5][nv][DIM], [4][nv][DIM]
-    const int32_t *vmapP;
-    T *Q, *A, *B, *G;
-    const double *clock;             // [t, step]
-    const KConst<T> *kc;
-    int *err;
-    double target;                   // step count at which the request stops
+    GB_GLOBAL const int32_t *etov;
+    GB_GLOBAL const double *vstage, *wstage;   // [5][nv][DIM], [4][nv][DIM]
+    GB_GLOBAL const int32_t *vmapP;
+    GB_GLOBAL T *Q, *A, *B, *G;
+    GB_GLOBAL const double *clock;             // [t, step]
+    GB_GLOBAL const KConst<T> *kc;
+    GB_GLOBAL int *err;
+    double target;                             // step count at which the request stops
 };
 
 template <typename T>
@@ -311,20 +316,20 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
         a.epb = 16;
         a.Nc = Nc;
         a.chunk = 0;
-        a.etov = E.etov;
+        a.etov = (const int32_t *)E.etov;
         const int slot = STAGE == kRhsOnly ? 0 : STAGE;
-        a.xs = E.vstage + int64_t(slot) * E.nv * DIM;
-        a.ws = E.wstage + int64_t(slot) * E.nv * DIM;
-        a.vmapP = E.vmapP;
+        a.xs = (const double *)(E.vstage + int64_t(slot) * E.nv * DIM);
+        a.ws = (const double *)(E.wstage + int64_t(slot) * E.nv * DIM);
+        a.vmapP = (const int32_t *)E.vmapP;
         a.ops = b.ops;
         a.fmask = b.fmask;
-        a.Q = E.Q;
-        a.A = E.A;
-        a.B = E.B;
-        a.G = E.G;
-        a.clock = E.clock;
-        a.kc = E.kc;
-        a.err = E.err;
+        a.Q = (T *)E.Q;
+        a.A = (T *)E.A;
+        a.B = (T *)E.B;
+        a.G = (T *)E.G;
+        a.clock = (const double *)E.clock;
+        a.kc = (const KConst<T> *)E.kc;
+        a.err = (int *)E.err;
         const KConst<T> &kc = *a.kc;
         const int g = gt - s_gb[r];
 #include "gb_stage_body.inc"

@@ -262,3 +262,30 @@ def test_batch_refuses_shapes_it_is_not_built_for():
     L.gb_batch_destroy(b)
     r.close()
     L.gb_ctx_destroy(ctx)
+
+
+def test_batch_large_member_stepped_on_its_own():
+    """A member with at least 2048 element groups gets a launch class of its
+    own (its stages back to back); its result, and the small members', equal
+    those of each request as the only member of a batch."""
+    ctx = L.gb_ctx_create(0, 0)
+    mix = [(make_case("C1", n=128, N=2), L.GB_FP32, 3),      # 32768 triangles = 2048 groups
+           (make_case("C1", n=8, N=2), L.GB_FP32, 4),
+           (make_case("C4", n_r=8, n_theta=16, N=2), L.GB_FP32, 2)]
+    ref = [_alone_batch(ctx, c, p, n) for c, p, n in mix]
+    reqs = [_Req(ctx, c, p) for c, p, _ in mix]
+    b = L.gb_batch_create(ctx, BIG)
+    for r, (c, p, n) in zip(reqs, mix):
+        L.gb_batch_add(b, r.solver, c.dt, n)
+    L.gb_batch_run(b, 1)
+    info = [L.gb_batch_class_info(b, i) for i in range(L.gb_batch_class_count(b))]
+    assert sorted((d["solo"], d["members"], d["groups"]) for d in info) == [(0, 2, 8 + 16), (1, 1, 2048)]
+    L.gb_batch_run(b, 3)
+    assert len(L.gb_batch_poll(b)) == 3
+    for i, r in enumerate(reqs):
+        q, t, step = r.state()
+        assert step == mix[i][2] and np.array_equal(q, ref[i][0]), i
+    L.gb_batch_destroy(b)
+    for r in reqs:
+        r.close()
+    L.gb_ctx_destroy(ctx)
