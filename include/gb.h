@@ -226,17 +226,20 @@ gb_status gb_solver_stage_time_by_kind(gb_solver *solver, double *avg_ms4);
 
 /* ------------------------------------------------------------------------
  * Batched form: many solvers (meshes of any size, orders and precisions on
- * one device) advanced together.  Each step of the batch is one captured HIP
- * graph: a vertex-motion launch per dimension; the four SARK-4 stages of
- * each large member in turn; for each of the four stages one launch per
- * class (same dimension, order, precision and cubature rule) over the
- * concatenated element groups of its smaller members; then the end-of-step
- * vertex update.  The kernels read a device request
+ * one device) advanced together.  A member large
+ * enough to fill the GPU (>= 2048 groups of 16 elements) is stepped on its
+ * own (vertex motion, the four SARK-4 stages, end-of-step update); the
+ * smaller members are stepped together from a captured HIP graph: one
+ * vertex launch per dimension,
+ * then for each stage one launch per class (same dimension, order,
+ * precision and cubature rule) over the concatenated element groups of its
+ * members.  The kernels read a device request
  * table (buffers, group offsets, constants, clock and target step of every
  * member); a member whose step counter has reached its target is skipped, so
- * members finish at different steps while the graph keeps replaying.  The
- * arithmetic per element is the same code as gb_sark_step, so a member's
- * result does not depend on what else is in the batch.
+ * members finish at different steps while the graph keeps replaying.  A
+ * member's result does not depend on what else is in the batch (bit for
+ * bit); it agrees with gb_sark_step to rounding (same per-element source,
+ * compiled in another kernel).
  *
  * Continuous batching: members join (gb_batch_add) and leave (gb_batch_poll)
  * at step boundaries; the table and the graph are rebuilt at the next
@@ -258,7 +261,11 @@ void gb_batch_destroy(gb_batch *batch);
  * read by other calls until gb_batch_poll has returned its ticket. */
 gb_status gb_batch_add(gb_batch *batch, gb_solver *solver, double dt, int64_t nsteps, uint64_t *ticket);
 
-/* Enqueue `steps` batch steps on the batch's stream (asynchronous). */
+/* Enqueue `steps` batch steps on the batch's stream (asynchronous), in
+ * rounds of k steps (k the largest divisor of `steps` up to 8): each large
+ * member takes its k steps in turn (direct launches), then the small members
+ * take theirs from a captured graph of k steps.  Members stop at their
+ * target step. */
 gb_status gb_batch_run(gb_batch *batch, int64_t steps);
 
 /* Synchronise, retire up to `capacity` members that reached their target

@@ -238,11 +238,12 @@ def gb_state_set(solver, q, t0: float = 0.0):
     _check(load().gb_state_set(solver, _dptr(q), t0))
 
 
-def gb_state_get(solver, shape):
-    q = np.zeros(shape)
+def gb_state_get(solver, shape=None):
+    """(state [K][NF][Np] or None when shape is None, time, steps taken)."""
+    q = None if shape is None else np.zeros(shape)
     t = C.c_double()
     step = _i64()
-    _check(load().gb_state_get(solver, _dptr(q), C.byref(t), C.byref(step)))
+    _check(load().gb_state_get(solver, None if q is None else _dptr(q), C.byref(t), C.byref(step)))
     return q, t.value, step.value
 
 

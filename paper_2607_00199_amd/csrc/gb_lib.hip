@@ -407,13 +407,21 @@ struct gb_batch {
         int64_t total = 0;          // element groups
         size_t lds = 0;
         int grid = 0;
+        int vset = -1;              // its vertex subset (solo classes)
         const void *ops = nullptr;
         const int32_t *fmask = nullptr;
     };
     std::vector<Class> classes;
-    DevBuf mot[2];                  // gbd::MotionEntry tables, 2D and 3D
-    int nmot[2] = {0, 0};
-    int64_t vtot[2] = {0, 0};
+    // vertex tables (gbd::MotionEntry), one subset per large member and one
+    // per dimension for the small members, stored back to back in `mot`
+    struct VertexSet {
+        int dim = 2, first = 0, n = 0;
+        int64_t vtot = 0;
+    };
+    DevBuf mot;
+    std::vector<VertexSet> vsets;
+    int vsmall[2] = {-1, -1};
+    int graph_steps = 0;            // steps held by the captured graph
     std::map<std::array<int, 5>, int> tuned;   // (dim, N, precision, Nc, solo) -> grid
     hipGraphExec_t graph = nullptr;
     bool dirty = true;
@@ -472,21 +480,23 @@ gbd::BatchLaunch class_launch(const gb_batch::Class &c, int grid) {
     return L;
 }
 
-hipError_t launch_vertex_batch(gb_batch *b, int di, bool finish, hipStream_t st) {
-    if (b->nmot[di] == 0) return hipSuccess;
+hipError_t launch_vertex_batch(gb_batch *b, int set, bool finish, hipStream_t st) {
+    if (set < 0) return hipSuccess;
+    const gb_batch::VertexSet &vs = b->vsets[size_t(set)];
+    if (vs.n == 0) return hipSuccess;
     const int blk = 256;
-    const unsigned nb = unsigned((b->vtot[di] + blk - 1) / blk);
-    const gbd::MotionEntry *E = b->mot[di].as<gbd::MotionEntry>();
-    if (di == 0) {
+    const unsigned nb = unsigned((vs.vtot + blk - 1) / blk);
+    const gbd::MotionEntry *E = b->mot.as<gbd::MotionEntry>() + vs.first;
+    if (vs.dim == 2) {
         if (finish)
-            hipLaunchKernelGGL(gbd::finish_batch_kernel<2>, dim3(nb), dim3(blk), 0, st, E, b->nmot[0], b->vtot[0]);
+            hipLaunchKernelGGL(gbd::finish_batch_kernel<2>, dim3(nb), dim3(blk), 0, st, E, vs.n, vs.vtot);
         else
-            hipLaunchKernelGGL(gbd::motion_batch_kernel<2>, dim3(nb), dim3(blk), 0, st, E, b->nmot[0], b->vtot[0]);
+            hipLaunchKernelGGL(gbd::motion_batch_kernel<2>, dim3(nb), dim3(blk), 0, st, E, vs.n, vs.vtot);
     } else {
         if (finish)
-            hipLaunchKernelGGL(gbd::finish_batch_kernel<3>, dim3(nb), dim3(blk), 0, st, E, b->nmot[1], b->vtot[1]);
+            hipLaunchKernelGGL(gbd::finish_batch_kernel<3>, dim3(nb), dim3(blk), 0, st, E, vs.n, vs.vtot);
         else
-            hipLaunchKernelGGL(gbd::motion_batch_kernel<3>, dim3(nb), dim3(blk), 0, st, E, b->nmot[1], b->vtot[1]);
+            hipLaunchKernelGGL(gbd::motion_batch_kernel<3>, dim3(nb), dim3(blk), 0, st, E, vs.n, vs.vtot);
     }
     return hipGetLastError();
 }
@@ -495,7 +505,7 @@ hipError_t launch_vertex_batch(gb_batch *b, int di, bool finish, hipStream_t st)
 // timed on the members' current state (see gb.h: state is not changed).
 gb_status tune_class(gb_batch *b, gb_batch::Class &c) {
     hipStream_t st = b->ctx->stream;
-    GB_HIP(launch_vertex_batch(b, c.dim - 2, false, st));
+    GB_HIP(launch_vertex_batch(b, c.solo ? c.vset : b->vsmall[c.dim - 2], false, st));
     const int mults[5] = {1, 2, 4, 8, 16};
     hipEvent_t e0, e1;
     GB_HIP(hipEventCreate(&e0));
@@ -577,16 +587,15 @@ gb_status batch_rebuild(gb_batch *b) {
         auto it = b->tuned.find({c.dim, c.N, c.prec, c.Nc, int(c.solo)});
         c.grid = it != b->tuned.end() ? it->second : b->ctx->num_cu * 2;
     }
-    for (int di = 0; di < 2; ++di) {
+    {
         std::vector<gbd::MotionEntry> E;
-        int64_t v = 0;
-        for (const auto &mb : b->members) {
+        b->vsets.clear();
+        auto entry = [&](const gb_batch::Member &mb, int64_t v0) {
             const gb_solver *s = mb.s;
             const gb_mesh *m = s->mesh;
-            if (m->dim != di + 2) continue;
             gbd::MotionEntry e{};
             e.nv = m->nv;
-            e.v_begin = v;
+            e.v_begin = v0;
             e.X = m->d_X.as<double>();
             e.x = m->d_x.as<double>();
             e.clock = s->clock.as<double>();
@@ -595,15 +604,43 @@ gb_status batch_rebuild(gb_batch *b) {
             e.dt = mb.dt;
             e.target = mb.target;
             e.m = m->motion;
-            E.push_back(e);
-            v += m->nv;
+            return e;
+        };
+        for (auto &c : b->classes) {
+            if (!c.solo) continue;
+            const gb_batch::Member &mb = b->members[size_t(c.idx[0])];
+            gb_batch::VertexSet vs;
+            vs.dim = c.dim;
+            vs.first = int(E.size());
+            vs.n = 1;
+            vs.vtot = mb.s->mesh->nv;
+            E.push_back(entry(mb, 0));
+            c.vset = int(b->vsets.size());
+            b->vsets.push_back(vs);
         }
-        if (int(E.size()) > gbd::kMaxBatch) return fail(GB_ERR_UNSUPPORTED, "too many members of one dimension");
-        b->nmot[di] = int(E.size());
-        b->vtot[di] = v;
+        for (int di = 0; di < 2; ++di) {
+            b->vsmall[di] = -1;
+            gb_batch::VertexSet vs;
+            vs.dim = di + 2;
+            vs.first = int(E.size());
+            for (const auto &c : b->classes) {
+                if (c.solo || c.dim != di + 2) continue;
+                for (int i : c.idx) {
+                    const gb_batch::Member &mb = b->members[size_t(i)];
+                    E.push_back(entry(mb, vs.vtot));
+                    vs.vtot += mb.s->mesh->nv;
+                    ++vs.n;
+                }
+            }
+            if (vs.n > gbd::kMaxBatch) return fail(GB_ERR_UNSUPPORTED, "too many small members of one dimension");
+            if (vs.n) {
+                b->vsmall[di] = int(b->vsets.size());
+                b->vsets.push_back(vs);
+            }
+        }
         if (!E.empty()) {
-            if (b->mot[di].alloc(E.size() * sizeof(E[0])) != hipSuccess) return fail(GB_ERR_OOM, "motion table");
-            GB_HIP(hipMemcpy(b->mot[di].p, E.data(), b->mot[di].bytes, hipMemcpyHostToDevice));
+            if (b->mot.alloc(E.size() * sizeof(E[0])) != hipSuccess) return fail(GB_ERR_OOM, "vertex tables");
+            GB_HIP(hipMemcpy(b->mot.p, E.data(), b->mot.bytes, hipMemcpyHostToDevice));
         }
     }
     if (b->autotune)
@@ -614,25 +651,55 @@ gb_status batch_rebuild(gb_batch *b) {
             if (r != GB_OK) return r;
             b->tuned[key] = c.grid;
         }
-    if (b->members.empty()) {
-        b->dirty = false;
-        return GB_OK;
+    b->dirty = false;
+    b->graph_steps = 0;
+    return GB_OK;
+}
+
+// `steps` steps of every large member in turn (motion, four stages, end of
+// step), launched directly: a member whose state fits the last-level cache
+// keeps it there from step to step, and its kernels are long enough that
+// launch overhead does not matter.
+hipError_t batch_launch_solo(gb_batch *b, int steps, hipStream_t st) {
+    hipError_t le = hipSuccess;
+    for (auto &c : b->classes) {
+        if (!c.solo) continue;
+        for (int k = 0; k < steps && le == hipSuccess; ++k) {
+            le = launch_vertex_batch(b, c.vset, false, st);
+            for (int kind = 0; kind < 4 && le == hipSuccess; ++kind)
+                le = c.shape.batch_stage(class_launch(c, c.grid), kind, st);
+            if (le == hipSuccess) le = launch_vertex_batch(b, c.vset, true, st);
+        }
     }
-    // one step as a graph, captured on a private stream
+    return le;
+}
+
+bool has_small(const gb_batch *b) {
+    for (const auto &c : b->classes)
+        if (!c.solo) return true;
+    return false;
+}
+
+// The graph of `steps` steps of the small members (one launch per class and
+// stage), captured on a private stream.
+gb_status batch_capture(gb_batch *b, int steps) {
+    if (b->graph) {
+        GB_HIP(hipGraphExecDestroy(b->graph));
+        b->graph = nullptr;
+    }
     hipStream_t cap;
     GB_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
-        for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, di, false, cap);
-        for (auto &c : b->classes)
-            for (int kind = 0; kind < 4 && le == hipSuccess && c.solo; ++kind)
-                le = c.shape.batch_stage(class_launch(c, c.grid), kind, cap);
-        for (int kind = 0; kind < 4 && le == hipSuccess; ++kind)
-            for (auto &c : b->classes)
-                if (le == hipSuccess && !c.solo) le = c.shape.batch_stage(class_launch(c, c.grid), kind, cap);
-        for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, di, true, cap);
+        for (int k = 0; k < steps && le == hipSuccess; ++k) {
+            for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, b->vsmall[di], false, cap);
+            for (int kind = 0; kind < 4 && le == hipSuccess; ++kind)
+                for (auto &c : b->classes)
+                    if (le == hipSuccess && !c.solo) le = c.shape.batch_stage(class_launch(c, c.grid), kind, cap);
+            for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, b->vsmall[di], true, cap);
+        }
         e = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess && le != hipSuccess) {
             (void)hipGraphDestroy(g);
@@ -644,7 +711,7 @@ gb_status batch_rebuild(gb_batch *b) {
     e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(GB_ERR_DEVICE, std::string("batch graph instantiate: ") + hipGetErrorString(e));
-    b->dirty = false;
+    b->graph_steps = steps;
     return GB_OK;
 }
 
@@ -1203,8 +1270,24 @@ gb_status gb_batch_run(gb_batch *b, int64_t steps) {
         if (r != GB_OK) return r;
     }
     if (b->members.empty() || steps == 0) return GB_OK;
+    // the graph holds k steps, k the largest divisor of `steps` up to 8
+    int k = 1;
+    for (int d = 8; d >= 1; --d)
+        if (steps % d == 0) {
+            k = d;
+            break;
+        }
     GB_HIP(hipSetDevice(b->ctx->device));
-    for (int64_t k = 0; k < steps; ++k) GB_HIP(hipGraphLaunch(b->graph, b->ctx->stream));
+    const bool small = has_small(b);
+    if (small && (!b->graph || b->graph_steps != k)) {
+        GB_HIP(hipStreamSynchronize(b->ctx->stream));
+        const gb_status r = batch_capture(b, k);
+        if (r != GB_OK) return r;
+    }
+    for (int64_t n = 0; n < steps / k; ++n) {
+        GB_HIP(batch_launch_solo(b, k, b->ctx->stream));
+        if (small) GB_HIP(hipGraphLaunch(b->graph, b->ctx->stream));
+    }
     return GB_OK;
 }
 

@@ -1,16 +1,19 @@
 """Served form: a request loop over the batched C ABI.
 
 Requests (each a mesh, order, precision, parameters and a step count) arrive
-over time.  At every step boundary of the batch the loop
+over time.  The loop runs the batch a few steps at a time (gb_batch_run,
+asynchronous) and, while those steps run on the GPU,
 
-  * admits arrived requests in arrival order while the request's device
-    footprint (gb_solver_footprint + gb_mesh_footprint) fits the free part of
-    the budget (a request that does not fit waits, and so does every request
-    behind it);
-  * runs the batch for a few steps (gb_batch_run, asynchronous; meshes of
-    newly arrived requests are built on the host meanwhile);
-  * retires the requests that reached their step count (gb_batch_poll) and
-    records completion - arrival as their latency.
+  * builds the meshes of newly arrived requests;
+  * prepares the next admissions in arrival order: a request is taken while
+    its device footprint (gb_solver_footprint + gb_mesh_footprint) fits the
+    free part of the budget (one that does not fit waits, and so does every
+    request behind it); its solver is created and its initial state uploaded
+    on a separate stream;
+
+then, at the step boundary, retires the requests that reached their step
+count (gb_batch_poll; latency = completion - arrival) and adds the prepared
+ones to the batch (gb_batch_add).
 
 A request's state stays on the device from admission to completion.  This
 module only marshals arguments and keeps the books; every step of every
@@ -125,17 +128,18 @@ class Server:
         K, Np, NF, _, _ = L.gb_mesh_sizes(r._mesh)
         r.dof = K * Np * NF
 
-    def _start(self, r: Request) -> int:
+    def _stage(self, r: Request):
+        """Solver and initial state of an admitted request (setup stream)."""
         r._solver = L.gb_solver_create(r._mesh, r._params)
         L.gb_state_set(r._solver, initial_state(r.case, r._mesh))
-        return L.gb_batch_add(self.batch, r._solver, r.case.dt, r.nsteps)
 
     def _finish(self, r: Request):
-        K, Np, NF, _, _ = L.gb_mesh_sizes(r._mesh)
-        q, t, step = L.gb_state_get(r._solver, (K, NF, Np))
-        r.t_final, r.steps_done = t, step
+        shape = None
         if r.keep_state:
-            r.state = q
+            K, Np, NF, _, _ = L.gb_mesh_sizes(r._mesh)
+            shape = (K, NF, Np)
+        q, t, step = L.gb_state_get(r._solver, shape)
+        r.t_final, r.steps_done, r.state = t, step, q
         self._release(r)
 
     def _release(self, r: Request):
@@ -149,11 +153,13 @@ class Server:
     # -------------------------------------------------------------- loop
     def serve(self, requests, clock=time.perf_counter, sleep=time.sleep) -> dict:
         pend = deque(sorted(requests, key=lambda q: q.arrival))
-        queue: deque = deque()
+        queue: deque = deque()          # arrived, not yet admitted
+        staged: list = []               # admitted, solver ready, not yet in the batch
         active: dict = {}
         finished = []
         t0 = clock()
-        while pend or queue or active:
+
+        def intake():
             now = clock() - t0
             while pend and pend[0].arrival <= now:
                 queue.append(pend.popleft())
@@ -161,12 +167,19 @@ class Server:
                 if r._mesh is None:
                     self._prepare(r)
             _, used, _ = L.gb_batch_info(self.batch)
-            n = admit_fifo([r.bytes for r in queue], self.budget - used)
-            for _ in range(n):
+            free = self.budget - used - sum(r.bytes for r in staged)
+            for _ in range(admit_fifo([r.bytes for r in queue], free)):
                 r = queue.popleft()
-                ticket = self._start(r)
+                self._stage(r)
                 r.t_admit = clock() - t0
-                active[ticket] = r
+                staged.append(r)
+
+        while pend or queue or staged or active:
+            if not active:
+                intake()
+            for r in staged:
+                active[L.gb_batch_add(self.batch, r._solver, r.case.dt, r.nsteps)] = r
+            staged.clear()
             if not active:
                 if queue:
                     # nothing running and the head still does not fit: it never will
@@ -181,13 +194,7 @@ class Server:
             if not self.classes:
                 self.classes = [L.gb_batch_class_info(self.batch, i)
                                 for i in range(L.gb_batch_class_count(self.batch))]
-            # build the meshes of requests that arrived meanwhile while the GPU steps
-            now = clock() - t0
-            while pend and pend[0].arrival <= now:
-                queue.append(pend.popleft())
-            for r in queue:
-                if r._mesh is None:
-                    self._prepare(r)
+            intake()                     # overlaps the steps just enqueued
             for ticket in L.gb_batch_poll(self.batch, len(active)):
                 r = active.pop(ticket)
                 r.t_done = clock() - t0
