@@ -137,10 +137,19 @@ __host__ __device__ constexpr bool stage_in_lds() {
     return !(DIM == 3 && N >= 3 && sizeof(T) == 8);
 }
 
+// Blocks of the group's state staged per wavefront: two where they fit (the
+// stage input and a second array the stage combination needs: q_n and F0 in
+// stage 1, G in stage 3), one otherwise (triangles of order 5 in FP64: about
+// 47 KB of fragments plus 16 KB per block and wavefront).
+template <int DIM, int N, typename T>
+__host__ __device__ constexpr int stage_lds_arrays() {
+    return !stage_in_lds<DIM, N, T>() ? 0 : (sizeof(T) == 8 && DIM == 2 && N >= 5) ? 1 : 2;
+}
+
 template <int DIM, int N, typename T>
 __host__ __device__ inline size_t mfma_lds_bytes(int nct) {
     using S = Shape<DIM, N>;
-    const size_t state = stage_in_lds<DIM, N, T>() ? size_t(kWaves) * S::NF * S::NP * 16 * sizeof(T) : 0;
+    const size_t state = size_t(stage_lds_arrays<DIM, N, T>()) * kWaves * S::NF * S::NP * 16 * sizeof(T);
     return mfma_lds_state_offset<DIM, N, T>(nct) + state;
 }
 
@@ -204,7 +213,8 @@ stage_mfma_kernel(KArgs<T> a) {
     const int q4 = lane >> 4;
     const T *BARY = s_ops + O::bary(nct);
     constexpr int BLK = NF * NP * 16;
-    T *s_q = reinterpret_cast<T *>(smem + mfma_lds_state_offset<DIM, N, T>(nct)) + wave * BLK;
+    T *s_q = reinterpret_cast<T *>(smem + mfma_lds_state_offset<DIM, N, T>(nct)) +
+             wave * BLK * stage_lds_arrays<DIM, N, T>();
 
     int logical = blockIdx.x;
     if ((gridDim.x & 7) == 0) logical = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
@@ -297,7 +307,8 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
     const int q4 = lane >> 4;
     const T *BARY = s_ops + O::bary(nct);
     constexpr int BLK = NF * NP * 16;
-    T *s_q = reinterpret_cast<T *>(smem + mfma_lds_state_offset<DIM, N, T>(nct)) + wave * BLK;
+    T *s_q = reinterpret_cast<T *>(smem + mfma_lds_state_offset<DIM, N, T>(nct)) +
+             wave * BLK * stage_lds_arrays<DIM, N, T>();
 
     int logical = blockIdx.x;
     if ((gridDim.x & 7) == 0) logical = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
