@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp"],
-    "sha256": "424070331a137c166eba37f7dab22cad7a784fb2a58a7f093355343452eae642",
+    "sha256": "d98df7585841ef52ed31623a35d515161c6a5e09f11004480c4c2d92d97e62f3",
     "K": 131072,
-    "bytes_per_launch": 237849 * 1024,
+    "bytes_per_launch": 217496 * 1024,
 }
 
 
