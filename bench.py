@@ -218,7 +218,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+              "(the multi-GPU sharding is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.served:

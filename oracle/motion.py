@@ -16,8 +16,8 @@ Motion kinds (displacement d(X, t), x = X + d):
       d_x = A sin(2 pi t/T) sin(2 pi (Y+L/2)/L) sin(2 pi (Z+L/2)/L), and cyclic;
   * "plunge_blend_2d" -- the plunge y = Y - h0 sin(omega t) of Section 7.3,
       multiplied by a radial weight B(|X - centre|) that is 1 inside r_in and
-      falls to 0 at r_out by a cosine ramp (the weight is this build's choice:
-      the paper moves the whole grid rigidly).
+      falls to 0 at r_out by a cosine ramp (the weight is a choice made here so
+      the outer boundary stays fixed: the paper moves the whole grid rigidly).
 """
 from __future__ import annotations
 

@@ -97,7 +97,7 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
-                              "(run __graft_entry__.build() or python -m paper_2607_00199_amd.build)")
+                              "(run python -m paper_2607_00199_amd.build)")
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)
