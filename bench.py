@@ -118,6 +118,39 @@ def run_gpu(precision_name: str, steps: int, warmup: int, n: int, graph: bool = 
     }
 
 
+def run_other(name: str, steps: int, warmup: int) -> dict:
+    """FP32 throughput of another workload: the 3D moving Taylor-Green vortex
+    (663552 tetrahedra, N=3) or the plunging airfoil O-grid with walls, far
+    field and sponge (262144 triangles, N=4)."""
+    from paper_2607_00199_amd import _lib as L
+    from paper_2607_00199_amd.serve import case_params
+    from paper_2607_00199_amd.session import Session
+    from workloads import make_case
+
+    case = make_case(name)
+    prm = case_params(case, L.GB_FP32)
+    q_inf = list(prm.q_inf) if prm.sponge_sigma_max > 0 else None
+    sponge = ((prm.sponge_cx, prm.sponge_cy, prm.sponge_r0, prm.sponge_r1, prm.sponge_sigma_max)
+              if prm.sponge_sigma_max > 0 else None)
+    s = Session(case, precision=L.GB_FP32, device=0, stream=0, q_inf=q_inf, sponge=sponge)
+    s.set_state(s.initial_state())
+    s.step(case.dt, warmup)
+    L.gb_ctx_synchronize(s.ctx)
+    L.gb_solver_time_stages(s.solver, True)
+    t0 = time.perf_counter()
+    s.step(case.dt, steps)
+    L.gb_ctx_synchronize(s.ctx)
+    el = time.perf_counter() - t0
+    avg_ms, _ = L.gb_solver_stage_time(s.solver)
+    K, Np, NF, dim = s.K, s.Np, s.NF, case.dim
+    s.close()
+    b = algorithmic_bytes_per_launch(K, Np, NF, dim, 4)
+    return {"K": K, "N": case.N, "dim": dim, "dof": K * Np * NF, "steps": steps,
+            "gdof_stage_s": round(K * Np * NF * 4 * steps / el / 1e9, 3), "stage_avg_ms": round(avg_ms, 5),
+            "achieved_GBs": round(b / (avg_ms * 1e-3) / 1e9, 1),
+            "frac": round(b / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(seconds_budget: float = 15.0):
     """Time the oracle (unchanged) on a bounded sample of the workload: the
     32 x 32 copy of the same configuration (2048 triangles, N = 4), as many
@@ -208,6 +241,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 512 MiB buffer three times (reference for HBM byte counters)")
+    ap.add_argument("--all-configs", action="store_true",
+                    help="also measure the 3D Taylor-Green and plunging-airfoil workloads (FP32)")
     ap.add_argument("--served", action="store_true",
                     help="run the served request mix instead (continuous batching, latency percentiles)")
     ap.add_argument("--requests", type=int, default=64)
@@ -280,6 +315,9 @@ def main():
                        "stage_avg_ms": round(r64["stage_avg_ms"], 5),
                        "achieved_GBs": round(a64, 1), "frac": round(a64 / HBM_PEAK_GBS, 4)}
         out["fp32_vs_fp64_velocity_rel_err"] = float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64))
+    if args.all_configs:
+        out["other_configs"] = {"3D moving TGV, 663552 tets, N=3": run_other("C3", 20, 3),
+                                "plunging airfoil O-grid, 262144 triangles, N=4": run_other("C4", 50, 5)}
     if not args.no_cpu_baseline:
         cb = cpu_baseline()
         out["cpu_baseline"] = {"value": round(cb.get("gdof_stage_s", float("nan")), 6), "unit": "GDOF-stage/s",
