@@ -49,6 +49,7 @@ class Request:
     t_final: float = math.nan
     steps_done: int = 0
     rejected: bool = False
+    error: str | None = None        # latched device error reported at completion
     _mesh: object = None
     _solver: object = None
     _params: object = None
@@ -138,8 +139,13 @@ class Server:
         if r.keep_state:
             K, Np, NF, _, _ = L.gb_mesh_sizes(r._mesh)
             shape = (K, NF, Np)
-        q, t, step = L.gb_state_get(r._solver, shape)
-        r.t_final, r.steps_done, r.state = t, step, q
+        try:
+            q, t, step = L.gb_state_get(r._solver, shape)
+            r.t_final, r.steps_done, r.state = t, step, q
+        except L.GbError as ex:
+            # a latched error (non-physical state, inverted element) fails
+            # this request only
+            r.error = str(ex)
         self._release(r)
 
     def _release(self, r: Request):
@@ -200,7 +206,7 @@ class Server:
                 r.t_done = clock() - t0
                 self._finish(r)
                 finished.append(r)
-        done = [r for r in finished if not r.rejected]
+        done = [r for r in finished if not r.rejected and r.error is None]
         lat = [r.t_done - r.arrival for r in done]
         work = sum(4.0 * r.dof * r.nsteps for r in done)
         first = min((r.arrival for r in done), default=0.0)
@@ -208,6 +214,7 @@ class Server:
         span = max(last - first, 1e-12)
         return {"requests": len(requests), "completed": len(done),
                 "rejected": sum(r.rejected for r in finished),
+                "failed": sum(r.error is not None for r in finished),
                 "latency_s": latency_summary(lat),
                 "wait_s": latency_summary([r.t_admit - r.arrival for r in done]),
                 "makespan_s": span, "dof_stages": work, "gdof_stage_s": work / span / 1e9,

@@ -47,3 +47,141 @@ def test_latency_summary_nearest_rank():
     s = latency_summary([2.0])
     assert s["p50"] == s["p99"] == s["max"] == 2.0
     assert latency_summary([])["n"] == 0
+
+
+class _FakeLib:
+    """Stand-in for the library calls the served loop makes: a batch whose
+    steps take simulated time proportional to the active members' size; no
+    GPU, no arithmetic.  Records what the loop did."""
+
+    def __init__(self, sim, poisoned=()):
+        from paper_2607_00199_amd import _lib as L
+        self.GbError, self.GB_FP32, self.make_params = L.GbError, L.GB_FP32, L.make_params
+        self.sim, self.poisoned = sim, set(poisoned)
+        self.max_used, self.admitted, self.live = 0, [], 0
+
+    def gb_stream_create(self, device=0):
+        return 1
+
+    def gb_stream_destroy(self, s):
+        pass
+
+    def gb_ctx_create(self, device, stream):
+        return object()
+
+    def gb_ctx_destroy(self, ctx):
+        pass
+
+    def gb_batch_create(self, ctx, budget):
+        return {"budget": budget, "used": 0, "members": {}, "next": 1}
+
+    def gb_batch_destroy(self, b):
+        pass
+
+    def gb_batch_set_autotune(self, b, on):
+        pass
+
+    def gb_mesh_create(self, ctx, dim, N, vx, etov, period=None, face_tag=None):
+        self.live += 1
+        return {"K": len(etov), "dim": dim, "N": N}
+
+    def gb_mesh_destroy(self, m):
+        self.live -= 1
+
+    def gb_set_motion(self, m, kind, p):
+        pass
+
+    def gb_mesh_sizes(self, m):
+        Np = (m["N"] + 1) * (m["N"] + 2) // 2
+        return m["K"], Np, 6, m["N"] + 1, 3
+
+    def gb_mesh_nodes(self, m, dim):
+        K, Np, *_ = self.gb_mesh_sizes(m)
+        return np.zeros((K, dim, Np))
+
+    def gb_solver_footprint(self, m, prm):
+        return 1000 * m["K"]
+
+    def gb_mesh_footprint(self, m):
+        return 10 * m["K"]
+
+    def gb_solver_create(self, m, prm):
+        self.live += 1
+        return {"mesh": m, "step": 0}
+
+    def gb_solver_destroy(self, s):
+        self.live -= 1
+
+    def gb_state_set(self, s, q, t0=0.0):
+        pass
+
+    def gb_batch_add(self, b, s, dt, nsteps):
+        need = 1010 * s["mesh"]["K"]
+        if b["used"] + need > b["budget"]:
+            raise self.GbError(8, "busy")
+        b["used"] += need
+        self.max_used = max(self.max_used, b["used"])
+        t = b["next"]
+        b["next"] += 1
+        b["members"][t] = {"s": s, "target": s["step"] + nsteps, "need": need}
+        self.admitted.append(id(s))
+        return t
+
+    def gb_batch_info(self, b):
+        return len(b["members"]), b["used"], b["budget"]
+
+    def gb_batch_run(self, b, steps):
+        for _ in range(steps):
+            act = [m for m in b["members"].values() if m["s"]["step"] < m["target"]]
+            self.sim[0] += 1e-6 * sum(m["s"]["mesh"]["K"] for m in act)
+            for m in act:
+                m["s"]["step"] += 1
+
+    def gb_batch_poll(self, b, capacity=1024):
+        done = [t for t, m in b["members"].items() if m["s"]["step"] >= m["target"]][:capacity]
+        for t in done:
+            b["used"] -= b["members"].pop(t)["need"]
+        return done
+
+    def gb_batch_class_count(self, b):
+        return 0
+
+    def gb_state_get(self, s, shape=None):
+        if s["mesh"]["K"] in self.poisoned:
+            raise self.GbError(5, "non-positive or NaN density latched on the device")
+        return None, 0.0, s["step"]
+
+
+def test_served_loop_scheduling_with_a_fake_library(monkeypatch):
+    """Admission in arrival order without overtaking, the budget never
+    exceeded, every request completed, a request whose footprint exceeds the
+    whole budget rejected, and a request whose state fails reported as failed
+    without stopping the others."""
+    from paper_2607_00199_amd import serve as S
+    from workloads import make_case
+    sim = [0.0]
+    sizes = [4, 8, 6, 12, 4, 8, 30, 6, 4, 10]          # quads per side; 30 is too large for the budget
+    cases = [make_case("C1", n=n, N=2) for n in sizes]
+    poisoned_K = cases[5].K                              # the request with n=8 at index 5 ...
+    assert sum(c.K == poisoned_K for c in cases) == 2    # ... shares its size with index 1
+    fake = _FakeLib(sim, poisoned={poisoned_K})
+    monkeypatch.setattr(S, "L", fake)
+    budget = 1010 * (2 * 12 * 12 + 2 * 8 * 8)           # two large-ish requests at once
+    srv = S.Server(budget, steps_per_launch=3)
+    reqs = [S.Request(index=i, arrival=0.01 * i, case=c, nsteps=5 + i) for i, c in enumerate(cases)]
+
+    def sleep(dt):
+        sim[0] += dt
+
+    stats = srv.serve(reqs, clock=lambda: sim[0], sleep=sleep)
+    assert fake.max_used <= budget
+    assert stats["rejected"] == 1 and reqs[6].rejected
+    assert stats["failed"] == 2 and reqs[1].error and reqs[5].error
+    assert stats["completed"] == len(reqs) - 3
+    ok = [r for r in reqs if not r.rejected and r.error is None]
+    assert all(r.steps_done == r.nsteps for r in ok)
+    assert all(r.t_done >= r.t_admit >= r.arrival for r in ok)
+    # admitted in arrival order (the rejected one never admitted)
+    order = [r.index for r in sorted((r for r in reqs if not r.rejected), key=lambda r: r.t_admit)]
+    assert order == sorted(order)
+    assert fake.live == 0                                # every mesh and solver released
