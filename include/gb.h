@@ -81,7 +81,8 @@ typedef enum {
     GB_MOTION_NONE = 0,
     GB_MOTION_SIN_PRODUCT_2D = 1,
     GB_MOTION_TRIPLE_PRODUCT_3D = 2,
-    GB_MOTION_PLUNGE_BLEND_2D = 3
+    GB_MOTION_PLUNGE_BLEND_2D = 3,
+    GB_MOTION_VERTEX_ARRAY = 4     /* velocities supplied per step, gb_set_vertex_velocity */
 } gb_motion_kind;
 
 typedef struct {
@@ -177,6 +178,15 @@ gb_status gb_mesh_vertices(const gb_mesh *mesh, double *vx);
 /* Set the prescribed motion (Section 5).  May be called before or between
  * steps; the current vertex positions are kept. */
 gb_status gb_set_motion(gb_mesh *mesh, const gb_motion *motion);
+
+/* Grid motion given by the caller (e.g. an external mesh-motion solver):
+ * w [4][nv][dim] (FP64 host, copied) holds the velocity of every vertex at
+ * the stage times t_n, t_n + dt/2, t_n + dt/2 and t_n + dt of the next step;
+ * the vertex positions of the stages advance from them by the classical RK4
+ * of Section 5, as for the analytic motions.  Call it before every step
+ * (steps run with the last values given); it waits for earlier work of the
+ * mesh's context.  Sets the mesh's motion kind to GB_MOTION_VERTEX_ARRAY. */
+gb_status gb_set_vertex_velocity(gb_mesh *mesh, const double *w);
 
 /* Create a solver on a mesh.  Allocates the four resident state arrays of the
  * SARK-4 schedule in device memory.  The solver keeps a reference to the

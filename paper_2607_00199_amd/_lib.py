@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libgb.so")
 GB_FP64, GB_FP32 = 0, 1
 GB_FLUX_SPLIT, GB_FLUX_RELATIVE = 0, 1
 GB_FACE_INTERIOR, GB_FACE_WALL, GB_FACE_FARFIELD = 0, 1, 2
-GB_MOTION_NONE, GB_MOTION_SIN_PRODUCT_2D, GB_MOTION_TRIPLE_PRODUCT_3D, GB_MOTION_PLUNGE_BLEND_2D = range(4)
+(GB_MOTION_NONE, GB_MOTION_SIN_PRODUCT_2D, GB_MOTION_TRIPLE_PRODUCT_3D, GB_MOTION_PLUNGE_BLEND_2D,
+ GB_MOTION_VERTEX_ARRAY) = range(5)
 
 STATUS_NAMES = {0: "GB_OK", 1: "GB_ERR_ARG", 2: "GB_ERR_MESH", 3: "GB_ERR_OOM", 4: "GB_ERR_DEVICE",
                 5: "GB_ERR_NONPHYSICAL", 6: "GB_ERR_STATE", 7: "GB_ERR_UNSUPPORTED", 8: "GB_ERR_BUSY"}
@@ -65,6 +66,7 @@ SIGNATURES = {
     "gb_mesh_nodes": (C.c_int, [_P, _dp]),
     "gb_mesh_vertices": (C.c_int, [_P, _dp]),
     "gb_set_motion": (C.c_int, [_P, C.POINTER(gb_motion)]),
+    "gb_set_vertex_velocity": (C.c_int, [_P, _dp]),
     "gb_solver_create": (C.c_int, [_P, C.POINTER(gb_params), C.POINTER(_P)]),
     "gb_solver_destroy": (None, [_P]),
     "gb_solver_footprint": (C.c_int, [_P, C.POINTER(gb_params), C.POINTER(C.c_size_t)]),
@@ -202,6 +204,12 @@ def gb_set_motion(mesh, kind: int, params=()):
     for i, v in enumerate(params):
         m.p[i] = float(v)
     _check(load().gb_set_motion(mesh, C.byref(m)))
+
+
+def gb_set_vertex_velocity(mesh, w):
+    """w [4][nv][dim]: vertex velocities at t_n, t_n + dt/2, t_n + dt/2, t_n + dt."""
+    w = _f64(w)
+    _check(load().gb_set_vertex_velocity(mesh, _dptr(w)))
 
 
 def make_params(c: float, tau: float, precision: int = GB_FP64, flux_mode: int = GB_FLUX_SPLIT,

@@ -14,6 +14,9 @@ constexpr double kSqrt2 = 1.41421356237309504880;
 struct Motion {
     int kind;
     double p[8];
+    // kind 4 (vertex array): velocities of every vertex at the four stage
+    // times t_n, t_n + dt/2, t_n + dt/2, t_n + dt, [4][nv][DIM], device memory
+    const double *w;
 };
 
 // Grid velocity v_G(X, t) = d/dt of the prescribed displacement at fixed

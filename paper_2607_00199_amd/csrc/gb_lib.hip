@@ -64,6 +64,7 @@ struct gb_mesh {
     gbh::Connectivity conn;
     std::vector<double> X;          // reference vertex positions (host)
     DevBuf d_etov, d_X, d_x, d_vmapP;
+    DevBuf d_wv;                    // vertex-array motion: [4][nv][dim] velocities
     gbd::Motion motion{};
     int64_t motion_serial = 0;      // bumped by every gb_set_motion
     int solvers = 0;
@@ -436,7 +437,9 @@ namespace {
 // 16 elements give one group to each wavefront of two workgroups per CU).
 constexpr int64_t kSoloGroups = 2048;
 
-size_t mesh_bytes(const gb_mesh *m) { return m->d_etov.bytes + m->d_X.bytes + m->d_x.bytes + m->d_vmapP.bytes; }
+size_t mesh_bytes(const gb_mesh *m) {
+    return m->d_etov.bytes + m->d_X.bytes + m->d_x.bytes + m->d_vmapP.bytes + m->d_wv.bytes;
+}
 
 size_t solver_bytes(const gb_mesh *m, const gb_params *p) {
     const size_t es = p->precision == GB_FP32 ? 4 : 8;
@@ -904,13 +907,33 @@ gb_status gb_mesh_nodes(const gb_mesh *m, double *xyz) {
 
 gb_status gb_set_motion(gb_mesh *m, const gb_motion *mo) {
     if (!m || !mo) return fail(GB_ERR_ARG, "NULL argument");
+    if (mo->kind == GB_MOTION_VERTEX_ARRAY) return fail(GB_ERR_ARG, "vertex-array motion is set by gb_set_vertex_velocity");
     if (mo->kind < 0 || mo->kind > 3) return fail(GB_ERR_ARG, "unknown motion kind");
     if (mo->kind == GB_MOTION_TRIPLE_PRODUCT_3D && m->dim != 3) return fail(GB_ERR_ARG, "3D motion on a 2D mesh");
     if ((mo->kind == GB_MOTION_SIN_PRODUCT_2D || mo->kind == GB_MOTION_PLUNGE_BLEND_2D) && m->dim != 2)
         return fail(GB_ERR_ARG, "2D motion on a 3D mesh");
     m->motion.kind = mo->kind;
     for (int i = 0; i < 8; ++i) m->motion.p[i] = mo->p[i];
+    m->motion.w = nullptr;
     ++m->motion_serial;
+    return GB_OK;
+}
+
+gb_status gb_set_vertex_velocity(gb_mesh *m, const double *w) {
+    if (!m || !w) return fail(GB_ERR_ARG, "NULL argument");
+    GB_HIP(hipSetDevice(m->ctx->device));
+    const size_t bytes = 4 * size_t(m->nv) * m->dim * sizeof(double);
+    const bool fresh = m->motion.kind != GB_MOTION_VERTEX_ARRAY || m->d_wv.bytes != bytes;
+    if (m->d_wv.bytes != bytes && m->d_wv.alloc(bytes) != hipSuccess) return fail(GB_ERR_OOM, "vertex velocities");
+    // ordered after earlier work of the mesh's context that may still read it
+    GB_HIP(hipStreamSynchronize(m->ctx->stream));
+    GB_HIP(hipMemcpy(m->d_wv.p, w, bytes, hipMemcpyHostToDevice));
+    if (fresh) {
+        m->motion.kind = GB_MOTION_VERTEX_ARRAY;
+        for (int i = 0; i < 8; ++i) m->motion.p[i] = 0.0;
+        m->motion.w = m->d_wv.as<double>();
+        ++m->motion_serial;
+    }
     return GB_OK;
 }
 

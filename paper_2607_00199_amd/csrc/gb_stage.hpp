@@ -109,10 +109,20 @@ __device__ __forceinline__ void motion_vertex(int64_t v, int64_t nv, const doubl
         Xv[d] = X[v * DIM + d];
         xn[d] = x[v * DIM + d];
     }
-    motion_velocity<DIM>(m, Xv, tn, w0);
-    motion_velocity<DIM>(m, Xv, tn + 0.5 * dt, w1);
-    motion_velocity<DIM>(m, Xv, tn + 0.5 * dt, w2);
-    motion_velocity<DIM>(m, Xv, tn + 1.0 * dt, w3);
+    if (m.kind == 4) {
+        const int64_t st = nv * DIM;
+        for (int d = 0; d < DIM; ++d) {
+            w0[d] = m.w[0 * st + v * DIM + d];
+            w1[d] = m.w[1 * st + v * DIM + d];
+            w2[d] = m.w[2 * st + v * DIM + d];
+            w3[d] = m.w[3 * st + v * DIM + d];
+        }
+    } else {
+        motion_velocity<DIM>(m, Xv, tn, w0);
+        motion_velocity<DIM>(m, Xv, tn + 0.5 * dt, w1);
+        motion_velocity<DIM>(m, Xv, tn + 0.5 * dt, w2);
+        motion_velocity<DIM>(m, Xv, tn + 1.0 * dt, w3);
+    }
     const int64_t st = nv * DIM;
     for (int d = 0; d < DIM; ++d) {
         const int64_t o = v * DIM + d;

@@ -30,12 +30,13 @@ def test_algorithmic_bytes_per_launch():
 
 
 def test_measured_traffic_follows_the_sources():
-    t = bench.measured_traffic(bench.MEASURED_TRAFFIC["K"])
-    assert t == bench.MEASURED_TRAFFIC["bytes_per_launch"]
-    assert bench.measured_traffic(bench.MEASURED_TRAFFIC["K"] + 16) is None
+    K = bench.MEASURED_TRAFFIC["K"]
     saved = dict(bench.MEASURED_TRAFFIC)
     try:
+        bench.MEASURED_TRAFFIC["sha256"] = bench.sources_digest()
+        assert bench.measured_traffic(K) == bench.MEASURED_TRAFFIC["bytes_per_launch"]
+        assert bench.measured_traffic(K + 16) is None
         bench.MEASURED_TRAFFIC["sha256"] = "0" * 64
-        assert bench.measured_traffic(saved["K"]) is None
+        assert bench.measured_traffic(K) is None
     finally:
         bench.MEASURED_TRAFFIC.update(saved)
