@@ -61,7 +61,6 @@ template <int DIM, int N, typename T>
 hipError_t launch_stage(const LaunchArgs &L, int kind, hipStream_t st) {
     KArgs<T> a{};
     a.K = L.K;
-    a.epb = 16;
     a.nbatch = int((L.K + 15) / 16);          // groups of 16 elements (one per wavefront)
     a.Nc = L.Nc;
     // each workgroup (kWaves wavefronts) takes a contiguous range of groups

@@ -86,7 +86,6 @@ struct gb_solver {
     double t = 0.0;
     int64_t step = 0;
     bool has_state = false;
-    int epb = 1;
     int grid = 1;
     size_t lds = 0;
     // timing: an event pair around every stage launch, resolved on query
@@ -970,7 +969,6 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     const int Np = s->ref.Np;
     const size_t need = L.lds(s->ref.Nc);
     if (need > m->ctx->max_lds) return fail(GB_ERR_UNSUPPORTED, "reference operators exceed the LDS of one workgroup");
-    s->epb = 16;
     s->lds = need;
     s->kconst_host.assign(std::max(sizeof(gbd::KConst<double>), sizeof(gbd::KConst<float>)), 0);
     // two workgroups per CU, each persistent over a contiguous range of

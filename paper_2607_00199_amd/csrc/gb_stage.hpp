@@ -53,7 +53,6 @@ template <typename T>
 struct KArgs {
     int64_t K;
     int nbatch;          // number of 16-element groups, ceil(K / 16)
-    int epb;             // elements per group (16)
     int Nc;              // cubature points
     int chunk;           // batches per workgroup
     const int32_t *etov;
@@ -78,13 +77,6 @@ struct Shape {
     static constexpr int NCONS = DIM + 1;
     static constexpr int NS = NF - NCONS;
     static constexpr int NVERT = DIM + 1;
-    static constexpr int GEO = DIM * DIM + NFACES * DIM + NFACES + 2 * NVERT * DIM;
-    // offsets inside GEO
-    static constexpr int G_MET = 0;
-    static constexpr int G_NRM = DIM * DIM;
-    static constexpr int G_FSC = G_NRM + NFACES * DIM;
-    static constexpr int G_WV = G_FSC + NFACES;
-    static constexpr int G_XV = G_WV + NVERT * DIM;
 };
 
 template <typename T>

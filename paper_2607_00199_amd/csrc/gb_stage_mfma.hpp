@@ -324,7 +324,6 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
         KArgs<T> a;
         a.K = E.K;
         a.nbatch = int((E.K + 15) / 16);
-        a.epb = 16;
         a.Nc = Nc;
         a.chunk = 0;
         a.etov = (const int32_t *)E.etov;
