@@ -40,7 +40,17 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
     objs = []
-    for name in sorted(os.listdir(CSRC)):
+
+    def cost(name: str) -> int:
+        # heaviest translation units first (tetrahedra, high orders, FP64) so
+        # the longest compiles do not start last
+        parts = name.replace(".hip", "").split("_")
+        if name.startswith("gb_shape_") and len(parts) == 5:
+            dim, order, prec = int(parts[2]), int(parts[3]), parts[4]
+            return -(100 * dim + 10 * order + (1 if prec == "f64" else 0))
+        return 0
+
+    for name in sorted(os.listdir(CSRC), key=lambda n: (cost(n), n)):
         src = os.path.join(CSRC, name)
         obj = os.path.join(BUILD, name + ".o")
         if name.endswith(".hip"):
