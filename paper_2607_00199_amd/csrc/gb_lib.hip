@@ -159,16 +159,6 @@ void fill_kconst(gbd::KConst<T> &k, const gb_solver *s, double dt) {
     double fv[25];
     flux_vinv(fv);
     for (int p = 0; p < 25; ++p) k.fluxV[p] = T(fv[p]);
-    {
-        // (c M_n)^- = sum_p fluxA[p] M_n^p: interpolate min(c lambda, 0) on the spectrum
-        const double c = s->prm.c, s3 = std::sqrt(3.0);
-        const double g[5] = {-c * s3, -c, 0.0, 0.0, 0.0};
-        for (int p = 0; p < 5; ++p) {
-            double acc = 0.0;
-            for (int l = 0; l < 5; ++l) acc += fv[p * 5 + l] * g[l];
-            k.fluxA[p] = T(acc);
-        }
-    }
     for (int f = 0; f < 10; ++f) k.q_inf[f] = T(s->prm.q_inf[f] - (f == 0 ? rho0 : 0.0));
     k.sponge = s->prm.sponge_sigma_max > 0.0;
     k.sp_cx = s->prm.sponge_cx;

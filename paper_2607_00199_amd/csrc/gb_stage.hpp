@@ -13,10 +13,11 @@
 //   source    P Ntilde(I q) on the stress fields (cubature)
 //   update    the stage's SARK combination (four resident state arrays)
 // Upwinding: M_n (normal flux pattern) has spectrum in {-sqrt3,-1,0,1,sqrt3}
-// for every unit normal (2D and the 3D tensor system), so the upwind matrix
-// B~- = sum_lambda g(lambda) P_lambda is the degree-4 polynomial in M_n that
-// interpolates g on those five points; g(lambda) = min(c lambda, 0) +
-// min(-w.n, 0) (split) or min(c lambda - w.n, 0) (relative).
+// for every unit normal (2D and the 3D tensor system), so the upwind matrix is
+// B~- = sum_lambda g(lambda) P_lambda.  Split: g(lambda) = min(c lambda, 0) +
+// min(-w.n, 0), with the two negative eigenspaces spanned by explicit
+// eigenvectors.  Relative: g(lambda) = min(c lambda - w.n, 0), applied as the
+// degree-4 polynomial in M_n that interpolates g on those five points.
 #pragma once
 
 #include "gb_device.hpp"
@@ -40,8 +41,7 @@ struct KConst {
     StageCoef<T> cf[2];  // [0] density/momentum (no relaxation), [1] stresses
     T c, inv_tau, rho0;
     int flux_mode;       // 0 split, 1 relative
-    T fluxV[25];         // row p: coefficients of g -> power p of M_n
-    T fluxA[5];          // split mode: coefficients of (c M_n)^- as a polynomial in M_n
+    T fluxV[25];         // relative mode, row p: coefficients of g -> power p of M_n
     T q_inf[10];
     int sponge;
     double sp_cx, sp_cy, sp_r0, sp_r1, sp_smax;
