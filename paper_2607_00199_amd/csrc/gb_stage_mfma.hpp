@@ -159,15 +159,26 @@ __device__ __forceinline__ int64_t baddr(int64_t e, int k, int j) {
     return ((((e >> 4) * NF + k) * NP + j) << 4) + (e & 15);
 }
 
+// Solver constants are read through the constant address space: a launch
+// never writes them, so the compiler may fetch them with scalar loads into
+// scalar registers instead of reloading them per lane inside guarded code.
+#define GB_CONST __attribute__((address_space(4)))
+template <typename T>
+using KConstRef = const GB_CONST KConst<T> &;
+template <typename T>
+__device__ __forceinline__ KConstRef<T> kconst_ref(const KConst<T> *p) {
+    return *(const GB_CONST KConst<T> *)p;
+}
+
 // Stage input of field k at a blocked offset `off` (relative to the state
 // arrays' common base), formed from the resident arrays for the stage being
 // evaluated.
 template <int NCONS, int STAGE, typename T>
-__device__ __forceinline__ T stage_in_at(const T *Q, const T *A, const T *B, const KConst<T> &kc, int k, int64_t off) {
+__device__ __forceinline__ T stage_in_at(const T *Q, const T *A, const T *B, KConstRef<T> kc, int k, int64_t off) {
     if constexpr (STAGE == kStage0 || STAGE == kRhsOnly) {
         return Q[off];
     } else if constexpr (STAGE == kStage1) {
-        const StageCoef<T> &c = kc.cf[k < NCONS ? 0 : 1];
+        const auto &c = kc.cf[k < NCONS ? 0 : 1];
         return c.E1 * Q[off] + c.a10 * A[off];
     } else if constexpr (STAGE == kStage2) {
         (void)Q;
@@ -205,7 +216,7 @@ stage_mfma_kernel(KArgs<T> a) {
     for (int p = threadIdx.x; p < 2 * O::slots(); p += blockDim.x) s_slot[p] = a.fmask[p];
     __syncthreads();
 
-    const KConst<T> &kc = *a.kc;
+    KConstRef<T> kc = kconst_ref(a.kc);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwave = blockDim.x >> 6;
@@ -222,8 +233,25 @@ stage_mfma_kernel(KArgs<T> a) {
     int g_end = g_begin + a.chunk;
     if (g_end > a.nbatch) g_end = a.nbatch;
 
+    // Triangle kernels load the vertex ids and the first two trace-map
+    // entries of a wave's next group while the current group computes, so a
+    // group's vertex data is requested together with its stage input.
+    constexpr bool kPF = DIM == 2;
+    int32_t pf_vm[2] = {0, 0};
+    int32_t pf_vid[NVERT] = {};
+    auto prefetch = [&](int gn) {
+        const int32_t *vmn = a.vmapP + int64_t(gn) * (O::slots() * 16) + q4 * 16 + col;
+        pf_vm[0] = vmn[0];
+        pf_vm[1] = NMS > 1 ? vmn[64] : 0;
+        const int64_t en = int64_t(gn) * 16 + col;
+#pragma unroll
+        for (int v = 0; v < NVERT; ++v) pf_vid[v] = a.etov[(en < a.K ? en : 0) * NVERT + v];
+    };
+    if (kPF && g_begin + wave < g_end) prefetch(g_begin + wave);
+
     for (int gi = g_begin + wave; gi < g_end; gi += nwave) {
         const int g = __builtin_amdgcn_readfirstlane(gi);
+        const int pf_next = gi + nwave < g_end ? g + nwave : -1;
 #include "gb_stage_body.inc"
     }
 }
@@ -340,8 +368,14 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
         a.clock = (const double *)E.clock;
         a.kc = (const KConst<T> *)E.kc;
         a.err = (int *)E.err;
-        const KConst<T> &kc = *a.kc;
+        KConstRef<T> kc = kconst_ref(a.kc);
         const int g = gt - s_gb[r];
+        // consecutive groups may belong to different entries: no look-ahead
+        constexpr bool kPF = false;
+        int32_t pf_vm[2] = {0, 0};
+        int32_t pf_vid[NVERT] = {};
+        const int pf_next = -1;
+        auto prefetch = [](int) {};
 #include "gb_stage_body.inc"
     }
 }
