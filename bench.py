@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp"],
-    "sha256": "30db395e6235652bb236ddf23957aac8e663c2067e58e103b14f4e3f7ed36f4a",
+    "sha256": "b8a94c5e544945d03c2b4795cbe60ff2a48d289a8e9a57273d974361ce47dcad",
     "K": 131072,
-    "bytes_per_launch": 218975 * 1024,
+    "bytes_per_launch": 218531 * 1024,
 }
 
 

@@ -344,11 +344,35 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
     int g_end = g_begin + b.chunk;
     if (g_end > b.total) g_end = b.total;
 
+    // As in stage_mfma_kernel, triangle kernels load the vertex ids and the
+    // first two trace-map entries of a wave's next group (found in the table,
+    // possibly another entry's) while the current group computes; after a
+    // skipped group they are loaded at the start of the next one.
+    constexpr bool kPF = DIM == 2;
+    int32_t pf_vm[2] = {0, 0};
+    int32_t pf_vid[NVERT] = {};
+    bool pf_ok = false;  // pf_vm and pf_vid hold the current group's entries
+    auto prefetch = [&](int gtn) {
+        const int rn = __builtin_amdgcn_readfirstlane(table_search(s_gb, b.nreq, gtn));
+        const BatchEntry<T> &En = ent[rn];
+        const int gn = gtn - s_gb[rn];
+        const int32_t *vmn = (const int32_t *)En.vmapP + int64_t(gn) * (O::slots() * 16) + q4 * 16 + col;
+        pf_vm[0] = vmn[0];
+        pf_vm[1] = NMS > 1 ? vmn[64] : 0;
+        const int64_t en = int64_t(gn) * 16 + col;
+        const int32_t *et = (const int32_t *)En.etov;
+#pragma unroll
+        for (int v = 0; v < NVERT; ++v) pf_vid[v] = et[(en < En.K ? en : 0) * NVERT + v];
+    };
+
     for (int gi = g_begin + wave; gi < g_end; gi += nwave) {
         const int gt = __builtin_amdgcn_readfirstlane(gi);
         const int r = __builtin_amdgcn_readfirstlane(table_search(s_gb, b.nreq, gt));
         const BatchEntry<T> &E = ent[r];
-        if (E.clock[1] >= E.target) continue;
+        if (E.clock[1] >= E.target) {
+            pf_ok = false;
+            continue;
+        }
         KArgs<T> a;
         a.K = E.K;
         a.nbatch = int((E.K + 15) / 16);
@@ -370,12 +394,10 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
         a.err = (int *)E.err;
         KConstRef<T> kc = kconst_ref(a.kc);
         const int g = gt - s_gb[r];
-        // consecutive groups may belong to different entries: no look-ahead
-        constexpr bool kPF = false;
-        int32_t pf_vm[2] = {0, 0};
-        int32_t pf_vid[NVERT] = {};
-        const int pf_next = -1;
-        auto prefetch = [](int) {};
+        if (kPF && !pf_ok) prefetch(gt);
+        // table index of this wave's next group (the body prefetches it)
+        const int pf_next = gi + nwave < g_end ? gt + nwave : -1;
+        pf_ok = pf_next >= 0;
 #include "gb_stage_body.inc"
     }
 }
