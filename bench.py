@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp"],
-    "sha256": "b8a94c5e544945d03c2b4795cbe60ff2a48d289a8e9a57273d974361ce47dcad",
+    "sha256": "232cb39281205855cef78372f79d1bc021ae1915c950b81d77ea24fc2bb7dc68",
     "K": 131072,
     "bytes_per_launch": 218531 * 1024,
 }
