@@ -16,7 +16,16 @@ anything the paper or mathematics fixes say "parity unpinned" in their
 docstring.
 
 Parity-unpinned parts (see the individual docstrings):
-  * the 3D 10-field moment system (the paper only cites it);
-  * the wall / far-field ghost states and the sponge layer used as a stand-in
-    for the paper's perfectly matched layer (the paper only names the PML).
+  * the 3D 10-field moment system (the paper only cites it) beyond its 2D
+    restriction, spectrum, conservation and covariance.
+The wall / far-field ghost states and the sponge layer are stand-ins for the
+paper's wall treatment and perfectly matched layer, which it names without
+giving their form: they are pinned by closed forms of their own definition
+(a uniform state moving with a rigid wall, a free stream, a uniform offset
+under the sponge), not by the paper.
+
+Modules: refelem (reference operators), mesh (connectivity), gbsystem (moment
+system), rhs (semi-discrete right-hand side), sark (time-integration
+coefficients), motion (prescribed mesh motions), solver (SARK-4 steps on the
+moving mesh), diagnostics (kinetic energy and its rate, wall force).
 """

@@ -17,7 +17,18 @@ Motion kinds (displacement d(X, t), x = X + d):
   * "plunge_blend_2d" -- the plunge y = Y - h0 sin(omega t) of Section 7.3,
       multiplied by a radial weight B(|X - centre|) that is 1 inside r_in and
       falls to 0 at r_out by a cosine ramp (the weight is a choice made here so
-      the outer boundary stays fixed: the paper moves the whole grid rigidly).
+      the outer boundary stays fixed: the paper moves the whole grid rigidly);
+  * "fish_3d" -- the carangiform swimming motion of Section 7.4 (eq.
+      fish_motion, eq. fish_amplitude_function and the blended mesh motion
+      that follows them), lengths in body lengths L = 1: only z moves,
+        d_z = A(xt) sin(phi) B(d_eff) S(t),
+        xt = min(1, max(0, X)),  A(xt) = a0 + a1 xt + a2 xt^2,
+        phi = 2 pi X / lam - 2 pi f t,
+        d_eff = max(|(X - xt, Y, Z)| - R_rigid, 0),  B = exp(-beta d_eff^2),
+        S = (1 - cos(pi t / T_ramp)) / 2 for t < T_ramp, else 1.
+      The paper prints the displacement with a factor "R" where the ramp S
+      belongs (its printed mesh velocity is the time derivative of the form
+      above); T_ramp <= 0 means no ramp.
 """
 from __future__ import annotations
 
@@ -72,6 +83,25 @@ class Motion:
             xi = np.clip((r - r0) / (r1 - r0), 0.0, 1.0)
             B = 0.5 * (1.0 + np.cos(math.pi * xi))
             out[:, 1] = -p["h0"] * tt * B
+            return out
+        if k == "fish_3d":
+            xt = np.clip(X[:, 0], 0.0, 1.0)
+            amp = p["a0"] + p["a1"] * xt + p["a2"] * xt * xt
+            om = 2 * math.pi * p["f"]
+            phi = 2 * math.pi * X[:, 0] / p["lam"] - om * t
+            dist = np.sqrt((X[:, 0] - xt) ** 2 + X[:, 1] ** 2 + X[:, 2] ** 2)
+            d_eff = np.maximum(dist - p["R_rigid"], 0.0)
+            B = np.exp(-p["beta"] * d_eff ** 2)
+            Tr = p["T_ramp"]
+            if Tr > 0 and t < Tr:
+                S = 0.5 * (1.0 - math.cos(math.pi * t / Tr))
+                dS = 0.5 * math.pi / Tr * math.sin(math.pi * t / Tr)
+            else:
+                S, dS = 1.0, 0.0
+            if deriv:
+                out[:, 2] = amp * B * (-om * np.cos(phi) * S + np.sin(phi) * dS)
+            else:
+                out[:, 2] = amp * np.sin(phi) * B * S
             return out
         raise ValueError(f"unknown motion kind {k!r}")
 
