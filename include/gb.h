@@ -76,13 +76,25 @@ enum { GB_FACE_INTERIOR = 0, GB_FACE_WALL = 1, GB_FACE_FARFIELD = 2 };
  *   PLUNGE_BLEND_2D  the plunge y = Y - h0 sin(omega t) of Section 7.3 times a
  *     radial weight B(r) = 1 for r <= p[2], cosine ramp to 0 at r = p[3],
  *     r = |X - (p[4], p[5])|; h0 = p[0], omega = p[1].  (The weight is this
- *     library's addition so the outer boundary stays fixed.) */
+ *     library's addition so the outer boundary stays fixed.)
+ *   FISH_3D  the carangiform swimming motion of Section 7.4 (eq. fish_motion,
+ *     eq. fish_amplitude_function and the blended mesh motion built on them),
+ *     lengths in body lengths, only z moves:
+ *       d_z = A(xt) sin(phi) B S(t),  xt = min(1, max(0, X)),
+ *       A = p[0] + p[1] xt + p[2] xt^2,  phi = 2 pi X / p[3] - 2 pi p[4] t,
+ *       B = exp(-p[6] d^2),  d = max(|(X - xt, Y, Z)| - p[5], 0),
+ *       S = (1 - cos(pi t / p[7])) / 2 for t < p[7], else 1 (p[7] <= 0: S = 1);
+ *     (a0, a1, a2, wavelength, tail-beat frequency, rigid-core radius, decay
+ *     rate, ramp time).  The paper prints the displacement with a factor R
+ *     where the ramp S belongs; its printed mesh velocity is d/dt of the
+ *     form above. */
 typedef enum {
     GB_MOTION_NONE = 0,
     GB_MOTION_SIN_PRODUCT_2D = 1,
     GB_MOTION_TRIPLE_PRODUCT_3D = 2,
     GB_MOTION_PLUNGE_BLEND_2D = 3,
-    GB_MOTION_VERTEX_ARRAY = 4     /* velocities supplied per step, gb_set_vertex_velocity */
+    GB_MOTION_VERTEX_ARRAY = 4,    /* velocities supplied per step, gb_set_vertex_velocity */
+    GB_MOTION_FISH_3D = 5
 } gb_motion_kind;
 
 typedef struct {
@@ -190,7 +202,9 @@ gb_status gb_set_vertex_velocity(gb_mesh *mesh, const double *w);
 
 /* Create a solver on a mesh.  Allocates the four resident state arrays of the
  * SARK-4 schedule in device memory.  The solver keeps a reference to the
- * mesh: destroy the solver first. */
+ * mesh: destroy the solver first.  A mesh carries the vertex positions its
+ * solver moves, so it takes one solver at a time: GB_ERR_STATE while another
+ * solver of the mesh exists. */
 gb_status gb_solver_create(gb_mesh *mesh, const gb_params *params, gb_solver **out);
 void gb_solver_destroy(gb_solver *solver);
 
@@ -202,8 +216,40 @@ gb_status gb_solver_footprint(const gb_mesh *mesh, const gb_params *params, size
 /* Device bytes held by the mesh (connectivity, trace map, vertex arrays). */
 gb_status gb_mesh_footprint(const gb_mesh *mesh, size_t *bytes);
 
-/* Set the state q [K][NF][Np] (FP64 host) and the time t0. */
+/* Set the state q [K][NF][Np] (FP64 host) and the time t0; resets the step
+ * counter to 0 and the vertex positions to the reference positions the mesh
+ * was created with (the configuration of the motion at time t0; the analytic
+ * motions have zero displacement at t = 0).  To resume a run with moved
+ * vertices use gb_checkpoint_load. */
 gb_status gb_state_set(gb_solver *solver, const double *q, double t0);
+
+/* Set the state to the equilibrium of the given density and velocity at
+ * every node (Section 2: rho = q1, rho u = c m, and the stress moments at
+ * which the collision term vanishes, S = m m^T / rho, stored with the
+ * diagonal as S_ii / sqrt2), plus an optional constant offset per field.
+ *   rho    [K][Np] density, > 0      u  [K][dim][Np] velocity
+ *   offset [NF] added to every node's moments after the equilibrium map, or
+ *          NULL (e.g. a uniform off-equilibrium stress)
+ * Computed on the device; time, step counter and vertex positions are reset
+ * as by gb_state_set.  GB_ERR_ARG if a density is not positive. */
+gb_status gb_state_set_equilibrium(gb_solver *solver, const double *rho, const double *u, const double *offset,
+                                   double t0);
+
+/* The same equilibrium map on the host, for states such as a far-field
+ * q_inf: rho [n], u [dim][n] -> q [NF][n].  No device work. */
+gb_status gb_equilibrium_moments(int dim, double c, int64_t n, const double *rho, const double *u, double *q);
+
+/* Checkpoint / resume.  A checkpoint is the solver's state in its storage
+ * precision (bit for bit), the current vertex positions, the time and the
+ * step counter, with a header of the mesh sizes.  Loading it into a solver
+ * of the same mesh (same vertices, elements, order, precision) and stepping
+ * n more steps gives bit for bit the result of stepping on without the
+ * checkpoint.  gb_checkpoint_bytes gives the buffer size; save synchronises;
+ * load checks the header (GB_ERR_ARG on a mismatch) and replaces state,
+ * positions, time and step counter. */
+gb_status gb_checkpoint_bytes(const gb_solver *solver, size_t *bytes);
+gb_status gb_checkpoint_save(gb_solver *solver, void *buf, size_t bytes);
+gb_status gb_checkpoint_load(gb_solver *solver, const void *buf, size_t bytes);
 
 /* Copy the state to the host (FP64 [K][NF][Np]); also returns the time and
  * the number of steps taken.  Synchronises and reports latched errors. */
@@ -212,8 +258,36 @@ gb_status gb_state_get(gb_solver *solver, double *q, double *t, int64_t *step);
 /* F = L(q) + P Ntilde(I q) for q [K][NF][Np] (FP64 host in and out) at the
  * current vertex positions, with the grid velocity at the current time: the
  * right-hand side of eq. time_split without the stiff -Lambda q part
- * (Section 4).  Does not change the solver state.  Synchronises. */
+ * (Section 4).  Does not change the solver state, its constants or its
+ * later steps.  Synchronises.  GB_ERR_STATE while the solver is a member of
+ * a batch. */
 gb_status gb_rhs(gb_solver *solver, const double *q, double *F);
+
+/* Kinetic energy and its dissipation rate (Section 7.2):
+ *   out[0] = E_K = (1 / (rho_inf |Omega|)) integral of rho u.u / 2,
+ *   out[1] = epsilon_1 = -dE_K/dt,  out[2] = |Omega| (current mesh volume),
+ * at the solver's current state, vertex positions and time.  The integral is
+ * taken element by element with the cubature rule of the relaxation term
+ * applied to the element's density and momentum (rho u = c m); dE_K/dt is
+ * the exact rate of that discrete energy along the semi-discrete system:
+ * the density and momentum change by F(q) (they have no stiff part) and the
+ * element Jacobians by J div(w), w the grid velocity at the current time.
+ * One right-hand-side evaluation (into a state array that is free between
+ * steps) and a two-pass device reduction in FP64 (deterministic: the same
+ * state gives the same bits).  Synchronises.  GB_ERR_STATE without a state
+ * or while the solver is a member of a batch. */
+gb_status gb_energy(gb_solver *solver, double rho_inf, double out[3]);
+
+/* Force of the fluid on the body: the integral over every wall face
+ * (GB_FACE_WALL) of p n (pressure, p = rho RT = c^2 rho) and of -sigma n
+ * (viscous, sigma the deviatoric stress of Section 2: sigma_ab =
+ * -c^2 (S_ab - m_a m_b / rho)), n the outward normal of the fluid element,
+ * at the current state and vertex positions.  out[0..dim) = pressure part,
+ * out[dim..2 dim) = viscous part.  The drag and lift coefficients of Section
+ * 7.3 are c_D = F_x / (rho_inf u_inf^2 chord / 2) and c_L likewise with F_y.
+ * Zero when the mesh has no wall face.  FP64 device reduction; synchronises.
+ * GB_ERR_STATE without a state or while the solver is a member of a batch. */
+gb_status gb_wall_force(gb_solver *solver, double *out);
 
 /* Advance nsteps SARK-4 steps of size dt (Section 4) on the context's
  * stream.  Asynchronous: returns after enqueueing.  The vertex positions

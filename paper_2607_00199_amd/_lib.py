@@ -21,7 +21,7 @@ GB_FP64, GB_FP32 = 0, 1
 GB_FLUX_SPLIT, GB_FLUX_RELATIVE = 0, 1
 GB_FACE_INTERIOR, GB_FACE_WALL, GB_FACE_FARFIELD = 0, 1, 2
 (GB_MOTION_NONE, GB_MOTION_SIN_PRODUCT_2D, GB_MOTION_TRIPLE_PRODUCT_3D, GB_MOTION_PLUNGE_BLEND_2D,
- GB_MOTION_VERTEX_ARRAY) = range(5)
+ GB_MOTION_VERTEX_ARRAY, GB_MOTION_FISH_3D) = range(6)
 
 STATUS_NAMES = {0: "GB_OK", 1: "GB_ERR_ARG", 2: "GB_ERR_MESH", 3: "GB_ERR_OOM", 4: "GB_ERR_DEVICE",
                 5: "GB_ERR_NONPHYSICAL", 6: "GB_ERR_STATE", 7: "GB_ERR_UNSUPPORTED", 8: "GB_ERR_BUSY"}
@@ -71,6 +71,13 @@ SIGNATURES = {
     "gb_solver_destroy": (None, [_P]),
     "gb_solver_footprint": (C.c_int, [_P, C.POINTER(gb_params), C.POINTER(C.c_size_t)]),
     "gb_state_set": (C.c_int, [_P, _dp, C.c_double]),
+    "gb_state_set_equilibrium": (C.c_int, [_P, _dp, _dp, _dp, C.c_double]),
+    "gb_equilibrium_moments": (C.c_int, [C.c_int, C.c_double, _i64, _dp, _dp, _dp]),
+    "gb_checkpoint_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "gb_checkpoint_save": (C.c_int, [_P, C.c_void_p, C.c_size_t]),
+    "gb_checkpoint_load": (C.c_int, [_P, C.c_void_p, C.c_size_t]),
+    "gb_energy": (C.c_int, [_P, C.c_double, _dp]),
+    "gb_wall_force": (C.c_int, [_P, _dp]),
     "gb_state_get": (C.c_int, [_P, _dp, _dp, C.POINTER(_i64)]),
     "gb_rhs": (C.c_int, [_P, _dp, _dp]),
     "gb_sark_step": (C.c_int, [_P, C.c_double, _i64]),
@@ -244,6 +251,49 @@ def gb_solver_footprint(mesh, params: gb_params) -> int:
 def gb_state_set(solver, q, t0: float = 0.0):
     q = _f64(q)
     _check(load().gb_state_set(solver, _dptr(q), t0))
+
+
+def gb_state_set_equilibrium(solver, rho, u, offset=None, t0: float = 0.0):
+    """rho [K][Np], u [K][dim][Np] (host FP64); offset [NF] or None."""
+    rho, u = _f64(rho), _f64(u)
+    off = None if offset is None else _f64(offset)
+    _check(load().gb_state_set_equilibrium(solver, _dptr(rho), _dptr(u), None if off is None else _dptr(off), t0))
+
+
+def gb_equilibrium_moments(dim: int, c: float, rho, u) -> np.ndarray:
+    """rho [n], u [dim][n] -> moments [NF][n] (host computation in the library)."""
+    rho = _f64(np.atleast_1d(rho))
+    u = _f64(np.asarray(u, float).reshape(dim, -1))
+    q = np.zeros((6 if dim == 2 else 10, rho.size))
+    _check(load().gb_equilibrium_moments(dim, c, rho.size, _dptr(rho), _dptr(u), _dptr(q)))
+    return q
+
+
+def gb_checkpoint_save(solver) -> bytes:
+    n = C.c_size_t()
+    _check(load().gb_checkpoint_bytes(solver, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(load().gb_checkpoint_save(solver, buf, n.value))
+    return buf.raw
+
+
+def gb_checkpoint_load(solver, data: bytes):
+    buf = C.create_string_buffer(data, len(data))
+    _check(load().gb_checkpoint_load(solver, buf, len(data)))
+
+
+def gb_energy(solver, rho_inf: float = 1.0):
+    """(E_K, epsilon_1 = -dE_K/dt, domain volume) at the current state."""
+    out = np.zeros(3)
+    _check(load().gb_energy(solver, rho_inf, _dptr(out)))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def gb_wall_force(solver, dim: int):
+    """(pressure force [dim], viscous force [dim]) of the fluid on the walls."""
+    out = np.zeros(2 * dim)
+    _check(load().gb_wall_force(solver, _dptr(out)))
+    return out[:dim].copy(), out[dim:].copy()
 
 
 def gb_state_get(solver, shape=None):

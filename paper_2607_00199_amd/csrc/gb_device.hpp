@@ -20,7 +20,7 @@ struct Motion {
 };
 
 // Grid velocity v_G(X, t) = d/dt of the prescribed displacement at fixed
-// reference position X (Section 5; motion formulas of Sections 7.1-7.3).
+// reference position X (Section 5; motion formulas of Sections 7.1-7.4).
 template <int DIM>
 __device__ __forceinline__ void motion_velocity(const Motion &m, const double *X, double t, double *w) {
     for (int d = 0; d < DIM; ++d) w[d] = 0.0;
@@ -50,6 +50,24 @@ __device__ __forceinline__ void motion_velocity(const Motion &m, const double *X
         xi = xi < 0.0 ? 0.0 : (xi > 1.0 ? 1.0 : xi);
         const double B = 0.5 * (1.0 + cos(kPi * xi));
         w[1] = -m.p[0] * tt * B;
+    } else if (m.kind == 5) {  // carangiform swimming (Section 7.4), z only
+        if constexpr (DIM == 3) {
+            const double xt = X[0] < 0.0 ? 0.0 : (X[0] > 1.0 ? 1.0 : X[0]);
+            const double amp = m.p[0] + m.p[1] * xt + m.p[2] * xt * xt;
+            const double om = 2.0 * kPi * m.p[4];
+            const double phi = 2.0 * kPi * X[0] / m.p[3] - om * t;
+            const double dx = X[0] - xt;
+            double dist = sqrt(dx * dx + X[1] * X[1] + X[2] * X[2]) - m.p[5];
+            dist = dist > 0.0 ? dist : 0.0;
+            const double B = exp(-m.p[6] * dist * dist);
+            double S = 1.0, dS = 0.0;
+            if (m.p[7] > 0.0 && t < m.p[7]) {
+                const double a = kPi / m.p[7];
+                S = 0.5 * (1.0 - cos(a * t));
+                dS = 0.5 * a * sin(a * t);
+            }
+            w[2] = amp * B * (-om * cos(phi) * S + sin(phi) * dS);
+        }
     }
 }
 

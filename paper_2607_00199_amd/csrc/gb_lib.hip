@@ -10,9 +10,11 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/gb.h"
+#include "gb_diag.hpp"
 #include "gb_launch.hpp"
 #include "host_ref.hpp"
 
@@ -65,6 +67,9 @@ struct gb_mesh {
     std::vector<double> X;          // reference vertex positions (host)
     DevBuf d_etov, d_X, d_x, d_vmapP;
     DevBuf d_wv;                    // vertex-array motion: [4][nv][dim] velocities
+    DevBuf d_wall;                  // wall faces, element * Nfaces + face
+    DevBuf d_fmask, d_wface;        // face node lists [Nfaces][Nfp] and their face-integral weights
+    int nwall = 0;
     gbd::Motion motion{};
     int64_t motion_serial = 0;      // bumped by every gb_set_motion
     int solvers = 0;
@@ -80,12 +85,15 @@ struct gb_solver {
     DevBuf ops, fmask, clock, err;
     DevBuf vstage, wstage;          // per-stage vertex positions [5][nv][dim] and velocities [4][nv][dim]
     DevBuf kconst;                  // gbd::KConst<T> for the current dt
+    DevBuf d_icub, d_wcub;          // cubature interpolation [Nc][Np] and weights [Nc], FP64 (diagnostics)
+    DevBuf diag;                    // energy reduction: per-workgroup partial sums, then the result
     std::vector<unsigned char> kconst_host;
     double kconst_dt = -1.0;
     int64_t kconst_motion_serial = -1;
     double t = 0.0;
     int64_t step = 0;
     bool has_state = false;
+    bool in_batch = false;          // a batch member: stepped and read only through its batch
     int grid = 1;
     size_t lds = 0;
     // timing: an event pair around every stage launch, resolved on query
@@ -324,6 +332,31 @@ gb_status check_error_flag(gb_solver *s) {
     if (flag & 1) return fail(GB_ERR_MESH, "an element was inverted (J <= 0) during stepping");
     if (flag & 2) return fail(GB_ERR_NONPHYSICAL, "non-positive or NaN density latched on the device");
     return GB_OK;
+}
+
+// Time t0, step 0, vertex positions back at the reference positions, error
+// latch cleared (after a new state has been enqueued on the context stream).
+gb_status reset_clock_and_positions(gb_solver *s, double t0) {
+    gb_mesh *m = s->mesh;
+    hipStream_t st = m->ctx->stream;
+    double clk[2] = {t0, 0.0};
+    GB_HIP(hipMemcpyAsync(s->clock.p, clk, sizeof(clk), hipMemcpyHostToDevice, st));
+    GB_HIP(hipMemcpyAsync(m->d_x.p, m->d_X.p, m->d_x.bytes, hipMemcpyDeviceToDevice, st));
+    GB_HIP(hipMemsetAsync(s->err.p, 0, sizeof(int), st));
+    GB_HIP(hipStreamSynchronize(st));
+    s->t = t0;
+    s->step = 0;
+    s->has_state = true;
+    return GB_OK;
+}
+
+// Solver constants that do not depend on the step size (flux mode, c, tau,
+// far field, sponge, motion): the right-hand-side-only launches read only
+// these, so a solver that has not stepped yet gets constants for dt = tau
+// (any dt would do) and one that has keeps its step size's coefficients.
+hipError_t ensure_consts(gb_solver *s, const Launcher &L, hipStream_t st) {
+    const double dt = s->kconst_dt > 0.0 ? s->kconst_dt : s->prm.tau;
+    return L.prepare(s, dt, st);
 }
 
 hipError_t launch_motion(gb_solver *s, double dt, hipStream_t st) {
@@ -850,6 +883,27 @@ gb_status gb_mesh_create(gb_ctx *ctx, int dim, int N, int64_t nv, const double *
             for (int mm = 0; mm < NFT; ++mm) blk[((e >> 4) * slots + mm) * 16 + (e & 15)] = m->conn.vmapP[e * NFT + mm];
         if (m->d_vmapP.alloc(blk.size() * sizeof(int32_t)) != hipSuccess) return fail(GB_ERR_OOM, "vmapP");
         GB_HIP(hipMemcpy(m->d_vmapP.p, blk.data(), m->d_vmapP.bytes, hipMemcpyHostToDevice));
+        // wall faces (trace map -1) for the force integral, the face node
+        // lists and the integral of each face node's Lagrange function over a
+        // face of measure 2: 1^T M LIFT (LIFT = M^-1 E, E the face mass)
+        std::vector<int32_t> wall;
+        const int Nfp = m->ref.Nfp, Nf = m->ref.Nfaces;
+        for (int64_t e = 0; e < K; ++e)
+            for (int f = 0; f < Nf; ++f)
+                if (m->conn.vmapP[(e * Nf + f) * Nfp] == -1) wall.push_back(int32_t(e * Nf + f));
+        m->nwall = int(wall.size());
+        std::vector<double> wface(size_t(NFT), 0.0);
+        for (int col = 0; col < NFT; ++col)
+            for (int i = 0; i < m->ref.Np; ++i)
+                for (int j = 0; j < m->ref.Np; ++j) wface[col] += m->ref.M(i, j) * m->ref.LIFT(j, col);
+        std::vector<int32_t> fm(m->ref.fmask.begin(), m->ref.fmask.end());
+        if (m->d_fmask.alloc(fm.size() * sizeof(int32_t)) != hipSuccess ||
+            m->d_wface.alloc(wface.size() * sizeof(double)) != hipSuccess ||
+            (!wall.empty() && m->d_wall.alloc(wall.size() * sizeof(int32_t)) != hipSuccess))
+            return fail(GB_ERR_OOM, "face tables");
+        GB_HIP(hipMemcpy(m->d_fmask.p, fm.data(), m->d_fmask.bytes, hipMemcpyHostToDevice));
+        GB_HIP(hipMemcpy(m->d_wface.p, wface.data(), m->d_wface.bytes, hipMemcpyHostToDevice));
+        if (!wall.empty()) GB_HIP(hipMemcpy(m->d_wall.p, wall.data(), m->d_wall.bytes, hipMemcpyHostToDevice));
     }
     m->motion.kind = 0;
     *out = m.release();
@@ -897,8 +951,10 @@ gb_status gb_mesh_nodes(const gb_mesh *m, double *xyz) {
 gb_status gb_set_motion(gb_mesh *m, const gb_motion *mo) {
     if (!m || !mo) return fail(GB_ERR_ARG, "NULL argument");
     if (mo->kind == GB_MOTION_VERTEX_ARRAY) return fail(GB_ERR_ARG, "vertex-array motion is set by gb_set_vertex_velocity");
-    if (mo->kind < 0 || mo->kind > 3) return fail(GB_ERR_ARG, "unknown motion kind");
-    if (mo->kind == GB_MOTION_TRIPLE_PRODUCT_3D && m->dim != 3) return fail(GB_ERR_ARG, "3D motion on a 2D mesh");
+    if (mo->kind < 0 || mo->kind > 5) return fail(GB_ERR_ARG, "unknown motion kind");
+    if ((mo->kind == GB_MOTION_TRIPLE_PRODUCT_3D || mo->kind == GB_MOTION_FISH_3D) && m->dim != 3)
+        return fail(GB_ERR_ARG, "3D motion on a 2D mesh");
+    if (mo->kind == GB_MOTION_FISH_3D && !(mo->p[3] != 0.0)) return fail(GB_ERR_ARG, "fish motion needs a wavelength");
     if ((mo->kind == GB_MOTION_SIN_PRODUCT_2D || mo->kind == GB_MOTION_PLUNGE_BLEND_2D) && m->dim != 2)
         return fail(GB_ERR_ARG, "2D motion on a 3D mesh");
     m->motion.kind = mo->kind;
@@ -944,6 +1000,8 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     if (!(p->c > 0.0) || !(p->tau > 0.0)) return fail(GB_ERR_ARG, "c and tau must be positive");
     if (p->precision != GB_FP64 && p->precision != GB_FP32) return fail(GB_ERR_ARG, "unknown precision");
     if (p->flux_mode != GB_FLUX_SPLIT && p->flux_mode != GB_FLUX_RELATIVE) return fail(GB_ERR_ARG, "unknown flux mode");
+    if (m->solvers > 0)
+        return fail(GB_ERR_STATE, "the mesh already has a solver (its vertex positions move with that solver)");
     auto s = std::make_unique<gb_solver>();
     s->mesh = m;
     s->prm = *p;
@@ -988,6 +1046,11 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     }
     if (s->fmask.alloc(slots.size() * sizeof(int32_t)) != hipSuccess) return fail(GB_ERR_OOM, "slot table");
     GB_HIP(hipMemcpy(s->fmask.p, slots.data(), s->fmask.bytes, hipMemcpyHostToDevice));
+    if (s->d_icub.alloc(s->ref.Icub.a.size() * sizeof(double)) != hipSuccess ||
+        s->d_wcub.alloc(s->ref.cub_w.size() * sizeof(double)) != hipSuccess)
+        return fail(GB_ERR_OOM, "cubature tables");
+    GB_HIP(hipMemcpy(s->d_icub.p, s->ref.Icub.a.data(), s->d_icub.bytes, hipMemcpyHostToDevice));
+    GB_HIP(hipMemcpy(s->d_wcub.p, s->ref.cub_w.data(), s->d_wcub.bytes, hipMemcpyHostToDevice));
     // padding elements of the last group stay zero
     for (DevBuf *b : {&s->Q, &s->A, &s->B, &s->G}) GB_HIP(hipMemset(b->p, 0, b->bytes));
     GB_HIP(hipMemset(s->err.p, 0, sizeof(int)));
@@ -1007,6 +1070,7 @@ void gb_solver_destroy(gb_solver *s) {
 
 gb_status gb_state_set(gb_solver *s, const double *q, double t0) {
     if (!s || !q) return fail(GB_ERR_ARG, "NULL argument");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
     gb_mesh *m = s->mesh;
     GB_HIP(hipSetDevice(m->ctx->device));
     const int64_t n = m->K * s->NF * s->ref.Np;
@@ -1023,12 +1087,159 @@ gb_status gb_state_set(gb_solver *s, const double *q, double t0) {
         hipLaunchKernelGGL(to_state_kernel<float>, dim3(nb), dim3(256), 0, st, tmp.as<double>(), s->Q.as<float>(), n,
                            s->ref.Np, s->NF, rho0);
     GB_HIP(hipGetLastError());
-    double clk[2] = {t0, 0.0};
-    GB_HIP(hipMemcpyAsync(s->clock.p, clk, sizeof(clk), hipMemcpyHostToDevice, st));
+    return reset_clock_and_positions(s, t0);
+}
+
+gb_status gb_state_set_equilibrium(gb_solver *s, const double *rho, const double *u, const double *offset,
+                                   double t0) {
+    if (!s || !rho || !u) return fail(GB_ERR_ARG, "NULL argument");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
+    gb_mesh *m = s->mesh;
+    GB_HIP(hipSetDevice(m->ctx->device));
+    const int64_t n = m->K * s->ref.Np;
+    const int dim = m->dim;
+    DevBuf tmp, bad;
+    if (tmp.alloc(size_t(n) * (1 + dim) * sizeof(double) + 10 * sizeof(double)) != hipSuccess ||
+        bad.alloc(sizeof(int)) != hipSuccess)
+        return fail(GB_ERR_OOM, "staging buffer");
+    hipStream_t st = m->ctx->stream;
+    double *d_rho = tmp.as<double>(), *d_u = d_rho + n, *d_off = d_u + n * dim;
+    GB_HIP(hipMemcpyAsync(d_rho, rho, size_t(n) * sizeof(double), hipMemcpyHostToDevice, st));
+    GB_HIP(hipMemcpyAsync(d_u, u, size_t(n) * dim * sizeof(double), hipMemcpyHostToDevice, st));
+    if (offset) GB_HIP(hipMemcpyAsync(d_off, offset, size_t(s->NF) * sizeof(double), hipMemcpyHostToDevice, st));
+    GB_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+    const unsigned nb = unsigned((n + 255) / 256);
+    const double rho0 = s->prm.precision == GB_FP32 ? s->prm.rho0 : 0.0;
+    const double *po = offset ? d_off : nullptr;
+    int *pb = bad.as<int>();
+    if (dim == 2 && s->prm.precision == GB_FP64)
+        hipLaunchKernelGGL((gbd::equilibrium_kernel<2, double>), dim3(nb), dim3(256), 0, st, d_rho, d_u, po, m->K,
+                           s->ref.Np, s->prm.c, 0.0, s->Q.as<double>(), pb);
+    else if (dim == 2)
+        hipLaunchKernelGGL((gbd::equilibrium_kernel<2, float>), dim3(nb), dim3(256), 0, st, d_rho, d_u, po, m->K,
+                           s->ref.Np, s->prm.c, rho0, s->Q.as<float>(), pb);
+    else if (s->prm.precision == GB_FP64)
+        hipLaunchKernelGGL((gbd::equilibrium_kernel<3, double>), dim3(nb), dim3(256), 0, st, d_rho, d_u, po, m->K,
+                           s->ref.Np, s->prm.c, 0.0, s->Q.as<double>(), pb);
+    else
+        hipLaunchKernelGGL((gbd::equilibrium_kernel<3, float>), dim3(nb), dim3(256), 0, st, d_rho, d_u, po, m->K,
+                           s->ref.Np, s->prm.c, rho0, s->Q.as<float>(), pb);
+    GB_HIP(hipGetLastError());
+    int flag = 0;
+    GB_HIP(hipMemcpyAsync(&flag, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipStreamSynchronize(st));
+    if (flag) {
+        s->has_state = false;
+        return fail(GB_ERR_ARG, "a density is not positive");
+    }
+    return reset_clock_and_positions(s, t0);
+}
+
+gb_status gb_equilibrium_moments(int dim, double c, int64_t n, const double *rho, const double *u, double *q) {
+    if (!rho || !u || !q) return fail(GB_ERR_ARG, "NULL argument");
+    if (dim != 2 && dim != 3) return fail(GB_ERR_ARG, "dim must be 2 or 3");
+    if (!(c > 0.0) || n < 0) return fail(GB_ERR_ARG, "c must be positive and n >= 0");
+    const double s2 = std::sqrt(2.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const double r = rho[i];
+        if (!(r > 0.0)) return fail(GB_ERR_ARG, "a density is not positive");
+        double m[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) m[d] = r * u[d * n + i] / c;
+        q[0 * n + i] = r;
+        for (int d = 0; d < dim; ++d) q[(1 + d) * n + i] = m[d];
+        if (dim == 2) {
+            q[3 * n + i] = m[0] * m[1] / r;
+            q[4 * n + i] = m[0] * m[0] / (s2 * r);
+            q[5 * n + i] = m[1] * m[1] / (s2 * r);
+        } else {
+            q[4 * n + i] = m[0] * m[1] / r;
+            q[5 * n + i] = m[0] * m[2] / r;
+            q[6 * n + i] = m[1] * m[2] / r;
+            q[7 * n + i] = m[0] * m[0] / (s2 * r);
+            q[8 * n + i] = m[1] * m[1] / (s2 * r);
+            q[9 * n + i] = m[2] * m[2] / (s2 * r);
+        }
+    }
+    return GB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+struct CheckpointHeader {
+    char magic[8];
+    int32_t dim, N, precision, NF;
+    int64_t K, nv, state_bytes, vertex_bytes;
+    double clock[2];
+};
+constexpr char kCheckpointMagic[8] = {'g', 'b', 'c', 'k', 'p', 't', '0', '1'};
+
+size_t state_storage_bytes(const gb_solver *s) {
+    return size_t((s->mesh->K + 15) / 16 * 16) * s->NF * s->ref.Np * s->elem_bytes;
+}
+}  // namespace
+
+extern "C" {
+
+gb_status gb_checkpoint_bytes(const gb_solver *s, size_t *bytes) {
+    if (!s || !bytes) return fail(GB_ERR_ARG, "NULL argument");
+    *bytes = sizeof(CheckpointHeader) + state_storage_bytes(s) + s->mesh->d_x.bytes;
+    return GB_OK;
+}
+
+gb_status gb_checkpoint_save(gb_solver *s, void *buf, size_t bytes) {
+    if (!s || !buf) return fail(GB_ERR_ARG, "NULL argument");
+    if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
+    size_t need = 0;
+    gb_checkpoint_bytes(s, &need);
+    if (bytes < need) return fail(GB_ERR_ARG, "checkpoint buffer too small");
+    gb_mesh *m = s->mesh;
+    GB_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t st = m->ctx->stream;
+    CheckpointHeader h{};
+    std::memcpy(h.magic, kCheckpointMagic, 8);
+    h.dim = m->dim;
+    h.N = m->N;
+    h.precision = s->prm.precision;
+    h.NF = s->NF;
+    h.K = m->K;
+    h.nv = m->nv;
+    h.state_bytes = int64_t(state_storage_bytes(s));
+    h.vertex_bytes = int64_t(m->d_x.bytes);
+    unsigned char *out = static_cast<unsigned char *>(buf);
+    GB_HIP(hipMemcpyAsync(h.clock, s->clock.p, sizeof(h.clock), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipMemcpyAsync(out + sizeof(h), s->Q.p, size_t(h.state_bytes), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipMemcpyAsync(out + sizeof(h) + h.state_bytes, m->d_x.p, size_t(h.vertex_bytes), hipMemcpyDeviceToHost,
+                          st));
+    GB_HIP(hipStreamSynchronize(st));
+    std::memcpy(out, &h, sizeof(h));
+    return check_error_flag(s);
+}
+
+gb_status gb_checkpoint_load(gb_solver *s, const void *buf, size_t bytes) {
+    if (!s || !buf) return fail(GB_ERR_ARG, "NULL argument");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
+    gb_mesh *m = s->mesh;
+    CheckpointHeader h;
+    if (bytes < sizeof(h)) return fail(GB_ERR_ARG, "checkpoint buffer too small");
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, kCheckpointMagic, 8) != 0) return fail(GB_ERR_ARG, "not a checkpoint");
+    if (h.dim != m->dim || h.N != m->N || h.precision != s->prm.precision || h.NF != s->NF || h.K != m->K ||
+        h.nv != m->nv || h.state_bytes != int64_t(state_storage_bytes(s)) || h.vertex_bytes != int64_t(m->d_x.bytes))
+        return fail(GB_ERR_ARG, "checkpoint of another mesh, order or precision");
+    if (bytes < sizeof(h) + size_t(h.state_bytes + h.vertex_bytes)) return fail(GB_ERR_ARG, "checkpoint truncated");
+    GB_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t st = m->ctx->stream;
+    const unsigned char *in = static_cast<const unsigned char *>(buf);
+    GB_HIP(hipMemcpyAsync(s->Q.p, in + sizeof(h), size_t(h.state_bytes), hipMemcpyHostToDevice, st));
+    GB_HIP(hipMemcpyAsync(m->d_x.p, in + sizeof(h) + h.state_bytes, size_t(h.vertex_bytes), hipMemcpyHostToDevice,
+                          st));
+    GB_HIP(hipMemcpyAsync(s->clock.p, h.clock, sizeof(h.clock), hipMemcpyHostToDevice, st));
     GB_HIP(hipMemsetAsync(s->err.p, 0, sizeof(int), st));
     GB_HIP(hipStreamSynchronize(st));
-    s->t = t0;
-    s->step = 0;
+    s->t = h.clock[0];
+    s->step = int64_t(h.clock[1]);
     s->has_state = true;
     return GB_OK;
 }
@@ -1036,6 +1247,7 @@ gb_status gb_state_set(gb_solver *s, const double *q, double t0) {
 gb_status gb_state_get(gb_solver *s, double *q, double *t, int64_t *step) {
     if (!s) return fail(GB_ERR_ARG, "NULL solver");
     if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
     gb_mesh *m = s->mesh;
     GB_HIP(hipSetDevice(m->ctx->device));
     hipStream_t st = m->ctx->stream;
@@ -1064,6 +1276,7 @@ gb_status gb_state_get(gb_solver *s, double *q, double *t, int64_t *step) {
 
 gb_status gb_rhs(gb_solver *s, const double *q, double *F) {
     if (!s || !q || !F) return fail(GB_ERR_ARG, "NULL argument");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
     gb_mesh *m = s->mesh;
     Launcher L;
     if (!get_launcher(m->dim, m->N, s->prm.precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel");
@@ -1087,7 +1300,7 @@ gb_status gb_rhs(gb_solver *s, const double *q, double *F) {
                            s->ref.Np, s->NF, rho0);
     GB_HIP(hipGetLastError());
     {
-        hipError_t pe = L.prepare(s, 0.0, st);
+        hipError_t pe = ensure_consts(s, L, st);
         if (pe != hipSuccess) return fail(GB_ERR_DEVICE, std::string("constants upload: ") + hipGetErrorString(pe));
     }
     {
@@ -1113,8 +1326,154 @@ gb_status gb_rhs(gb_solver *s, const double *q, double *F) {
     return check_error_flag(s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workgroups of the energy reduction: one wavefront per element, at most a
+// few workgroups per CU (the per-element work is small).
+int energy_grid(const gb_solver *s) {
+    const int64_t waves = s->mesh->K;
+    const int64_t per_block = gbd::kDiagBlock / 64;
+    return int(std::max<int64_t>(1, std::min<int64_t>(int64_t(s->mesh->ctx->num_cu) * 4,
+                                                      (waves + per_block - 1) / per_block)));
+}
+
+size_t energy_lds(const gb_solver *s) {
+    const int NC = s->mesh->dim + 1, Np = s->ref.Np, Nc = s->ref.Nc;
+    return sizeof(double) * (size_t(Nc) * Np + Nc + gbd::kDiagBlock + (gbd::kDiagBlock / 64) * 2 * NC * Np);
+}
+
+// Enqueue the energy diagnostic: the current geometry and grid velocity
+// (vertex kernel with dt = 0), F(q) into the free array A, the per-workgroup
+// partial sums into partial[grid][4] and {E_K, -dE_K/dt, |Omega|} into
+// result[3].  Needs the solver's constants on the device.
+gb_status enqueue_energy(gb_solver *s, const Launcher &L, double rho_inf, double *partial, double *result,
+                         hipStream_t st) {
+    gb_mesh *m = s->mesh;
+    GB_HIP(launch_motion(s, 0.0, st));
+    GB_HIP(L.stage(s, 4, 0.0, st));
+    const int grid = energy_grid(s);
+    const size_t lds = energy_lds(s);
+    const double rho0 = s->prm.precision == GB_FP32 ? s->prm.rho0 : 0.0;
+    auto run = [&](auto tag, auto dimc) -> hipError_t {
+        using T = decltype(tag);
+        constexpr int D = decltype(dimc)::value;
+        gbd::EnergyArgs<T> a{};
+        a.K = m->K;
+        a.Np = s->ref.Np;
+        a.NF = s->NF;
+        a.Nc = s->ref.Nc;
+        a.dim = D;
+        a.Q = s->Q.as<T>();
+        a.F = s->A.as<T>();
+        a.etov = m->d_etov.as<int32_t>();
+        a.x = s->vstage.as<double>();   // slot 0: the current positions
+        a.w = s->wstage.as<double>();   // slot 0: the grid velocity at the current time
+        a.Icub = s->d_icub.as<double>();
+        a.wcub = s->d_wcub.as<double>();
+        a.c = s->prm.c;
+        a.rho0 = rho0;
+        a.partial = partial;
+        hipLaunchKernelGGL((gbd::energy_partial_kernel<D, T>), dim3(grid), dim3(gbd::kDiagBlock), lds, st, a);
+        return hipGetLastError();
+    };
+    hipError_t e;
+    if (m->dim == 2)
+        e = s->prm.precision == GB_FP64 ? run(double{}, std::integral_constant<int, 2>{})
+                                        : run(float{}, std::integral_constant<int, 2>{});
+    else
+        e = s->prm.precision == GB_FP64 ? run(double{}, std::integral_constant<int, 3>{})
+                                        : run(float{}, std::integral_constant<int, 3>{});
+    GB_HIP(e);
+    hipLaunchKernelGGL(gbd::energy_final_kernel, dim3(1), dim3(gbd::kDiagBlock), 0, st, partial, grid, rho_inf,
+                       result);
+    GB_HIP(hipGetLastError());
+    return GB_OK;
+}
+
+gb_status check_diag_call(gb_solver *s, Launcher &L) {
+    if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
+    gb_mesh *m = s->mesh;
+    if (!get_launcher(m->dim, m->N, s->prm.precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel");
+    GB_HIP(hipSetDevice(m->ctx->device));
+    GB_HIP(ensure_consts(s, L, m->ctx->stream));
+    return GB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gb_status gb_energy(gb_solver *s, double rho_inf, double out[3]) {
+    if (!s || !out) return fail(GB_ERR_ARG, "NULL argument");
+    if (!(rho_inf > 0.0)) return fail(GB_ERR_ARG, "rho_inf must be positive");
+    Launcher L;
+    gb_status r = check_diag_call(s, L);
+    if (r != GB_OK) return r;
+    const int grid = energy_grid(s);
+    const size_t need = (size_t(grid) * gbd::kDiagSums + 4) * sizeof(double);
+    if (s->diag.bytes < need && s->diag.alloc(need) != hipSuccess) return fail(GB_ERR_OOM, "energy reduction buffer");
+    hipStream_t st = s->mesh->ctx->stream;
+    double *partial = s->diag.as<double>();
+    double *result = partial + size_t(grid) * gbd::kDiagSums;
+    r = enqueue_energy(s, L, rho_inf, partial, result, st);
+    if (r != GB_OK) return r;
+    GB_HIP(hipMemcpyAsync(out, result, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipStreamSynchronize(st));
+    return check_error_flag(s);
+}
+
+gb_status gb_wall_force(gb_solver *s, double *out) {
+    if (!s || !out) return fail(GB_ERR_ARG, "NULL argument");
+    Launcher L;
+    gb_status r = check_diag_call(s, L);
+    if (r != GB_OK) return r;
+    gb_mesh *m = s->mesh;
+    const int dim = m->dim;
+    for (int k = 0; k < 2 * dim; ++k) out[k] = 0.0;
+    if (m->nwall == 0) return GB_OK;
+    const size_t need = 8 * sizeof(double);
+    if (s->diag.bytes < need && s->diag.alloc(need) != hipSuccess) return fail(GB_ERR_OOM, "force reduction buffer");
+    hipStream_t st = m->ctx->stream;
+    const double rho0 = s->prm.precision == GB_FP32 ? s->prm.rho0 : 0.0;
+    auto run = [&](auto tag, auto dimc) -> hipError_t {
+        using T = decltype(tag);
+        constexpr int D = decltype(dimc)::value;
+        gbd::ForceArgs<T> a{};
+        a.nwall = m->nwall;
+        a.wall = m->d_wall.as<int32_t>();
+        a.Np = s->ref.Np;
+        a.NF = s->NF;
+        a.Nfp = s->ref.Nfp;
+        a.Q = s->Q.as<T>();
+        a.etov = m->d_etov.as<int32_t>();
+        a.x = m->d_x.as<double>();
+        a.fmask = m->d_fmask.as<int32_t>();
+        a.wface = m->d_wface.as<double>();
+        a.c = s->prm.c;
+        a.rho0 = rho0;
+        a.out = s->diag.as<double>();
+        hipLaunchKernelGGL((gbd::wall_force_kernel<D, T>), dim3(1), dim3(gbd::kDiagBlock), 0, st, a);
+        return hipGetLastError();
+    };
+    hipError_t e;
+    if (dim == 2)
+        e = s->prm.precision == GB_FP64 ? run(double{}, std::integral_constant<int, 2>{})
+                                        : run(float{}, std::integral_constant<int, 2>{});
+    else
+        e = s->prm.precision == GB_FP64 ? run(double{}, std::integral_constant<int, 3>{})
+                                        : run(float{}, std::integral_constant<int, 3>{});
+    GB_HIP(e);
+    GB_HIP(hipMemcpyAsync(out, s->diag.p, 2 * dim * sizeof(double), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipStreamSynchronize(st));
+    return check_error_flag(s);
+}
+
 gb_status gb_sark_step(gb_solver *s, double dt, int64_t nsteps) {
     if (!s) return fail(GB_ERR_ARG, "NULL solver");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
     if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
     if (!(dt > 0.0) || nsteps < 0) return fail(GB_ERR_ARG, "dt must be positive and nsteps >= 0");
     gb_mesh *m = s->mesh;
@@ -1133,6 +1492,7 @@ gb_status gb_sark_step(gb_solver *s, double dt, int64_t nsteps) {
 
 gb_status gb_sark_step_graph(gb_solver *s, double dt, int64_t nsteps) {
     if (!s) return fail(GB_ERR_ARG, "NULL solver");
+    if (s->in_batch) return fail(GB_ERR_STATE, "the solver is a member of a batch");
     if (!s->has_state) return fail(GB_ERR_STATE, "no state set");
     if (!(dt > 0.0) || nsteps < 0) return fail(GB_ERR_ARG, "dt must be positive and nsteps >= 0");
     gb_mesh *m = s->mesh;
@@ -1232,6 +1592,7 @@ void gb_batch_destroy(gb_batch *b) {
     if (!b) return;
     (void)hipSetDevice(b->ctx->device);
     (void)hipStreamSynchronize(b->ctx->stream);
+    for (auto &mb : b->members) mb.s->in_batch = false;
     delete b;
 }
 
@@ -1266,6 +1627,7 @@ gb_status gb_batch_add(gb_batch *b, gb_solver *s, double dt, int64_t nsteps, uin
     mb.target = clk[1] + double(nsteps);
     mb.ticket = b->next_ticket++;
     mb.bytes = bytes;
+    s->in_batch = true;
     b->members.push_back(mb);
     b->used += bytes;
     b->dirty = true;
@@ -1318,6 +1680,7 @@ gb_status gb_batch_poll(gb_batch *b, uint64_t *done, int capacity, int *n_done) 
             done[(*n_done)++] = mb.ticket;
             mb.s->t = clk[2 * i];
             mb.s->step = int64_t(clk[2 * i + 1]);
+            mb.s->in_batch = false;
             b->used -= mb.bytes;
             b->dirty = true;
         } else {

@@ -29,7 +29,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib as L
-from .session import equilibrium_moments, motion_params
+from .session import equilibrium_moments, initial_offset, motion_params
 
 
 @dataclass
@@ -94,12 +94,13 @@ def case_params(case, precision):
     return L.make_params(case.c, case.tau, precision, q_inf=q_inf, sponge=sponge)
 
 
-def initial_state(case, mesh) -> np.ndarray:
-    """Equilibrium moments of the case's initial macroscopic fields at the
-    mesh's nodes, [K, NF, Np]."""
+def set_initial_state(case, mesh, solver):
+    """The case's initial state (equilibrium of its macroscopic fields at the
+    mesh's nodes), formed by the library on the device."""
     X = L.gb_mesh_nodes(mesh, case.dim)
     rho, u = case.macroscopic(X)
-    return equilibrium_moments(case.dim, rho, u, case.c).transpose(1, 0, 2).copy()
+    NF = 6 if case.dim == 2 else 10
+    L.gb_state_set_equilibrium(solver, rho, np.stack(u, axis=1), initial_offset(case, NF))
 
 
 class Server:
@@ -132,7 +133,7 @@ class Server:
     def _stage(self, r: Request):
         """Solver and initial state of an admitted request (setup stream)."""
         r._solver = L.gb_solver_create(r._mesh, r._params)
-        L.gb_state_set(r._solver, initial_state(r.case, r._mesh))
+        set_initial_state(r.case, r._mesh, r._solver)
 
     def _finish(self, r: Request):
         shape = None
@@ -184,7 +185,15 @@ class Server:
             if not active:
                 intake()
             for r in staged:
-                active[L.gb_batch_add(self.batch, r._solver, r.case.dt, r.nsteps)] = r
+                try:
+                    active[L.gb_batch_add(self.batch, r._solver, r.case.dt, r.nsteps)] = r
+                except L.GbError as ex:
+                    # a request the batch cannot take (a shape the batched
+                    # kernel is not built for, a full table) fails on its own
+                    r.error = str(ex)
+                    r.t_done = clock() - t0
+                    self._release(r)
+                    finished.append(r)
             staged.clear()
             if not active:
                 if queue:
@@ -247,7 +256,7 @@ def serial_rate(req: Request, device: int = 0, steps: int = 20, warmup: int = 3)
         L.gb_set_motion(mesh, kind, p)
         s = L.gb_solver_create(mesh, case_params(c, req.precision))
         try:
-            L.gb_state_set(s, initial_state(c, mesh))
+            set_initial_state(c, mesh, s)
             L.gb_sark_step_graph(s, c.dt, warmup)
             L.gb_ctx_synchronize(ctx)
             t0 = time.perf_counter()

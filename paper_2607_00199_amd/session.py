@@ -4,13 +4,9 @@ Argument marshalling only; every step of the path runs in libgb.so.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
 from . import _lib as L
-
-SQ2 = math.sqrt(2.0)
 
 
 def motion_params(motion: dict):
@@ -28,19 +24,28 @@ def motion_params(motion: dict):
         cx, cy = motion.get("center", (0.0, 0.0))
         return L.GB_MOTION_PLUNGE_BLEND_2D, [motion["h0"], motion["omega"], motion["r_in"],
                                               motion["r_out"], cx, cy]
+    if k == "fish_3d":
+        return L.GB_MOTION_FISH_3D, [motion["a0"], motion["a1"], motion["a2"], motion["lam"], motion["f"],
+                                     motion["R_rigid"], motion["beta"], motion["T_ramp"]]
     raise ValueError(k)
 
 
 def equilibrium_moments(dim: int, rho, u, c: float) -> np.ndarray:
     """Moments [NF, ...] of the equilibrium state with density rho and
-    velocity u: rho u = c m, stresses S = m m^T / rho (diagonal stored as
-    S_ii / sqrt2)."""
+    velocity u (u[d] arrays of rho's shape), computed by the library."""
     rho = np.asarray(rho, float)
-    m = [rho * np.asarray(u[d], float) / c for d in range(dim)]
-    if dim == 2:
-        return np.stack([rho, m[0], m[1], m[0] * m[1] / rho, m[0] ** 2 / (SQ2 * rho), m[1] ** 2 / (SQ2 * rho)])
-    return np.stack([rho, m[0], m[1], m[2], m[0] * m[1] / rho, m[0] * m[2] / rho, m[1] * m[2] / rho,
-                     m[0] ** 2 / (SQ2 * rho), m[1] ** 2 / (SQ2 * rho), m[2] ** 2 / (SQ2 * rho)])
+    q = L.gb_equilibrium_moments(dim, c, rho.ravel(), np.stack([np.asarray(u[d], float).ravel() for d in range(dim)]))
+    return q.reshape((q.shape[0],) + rho.shape)
+
+
+def initial_offset(case, NF: int):
+    """Per-field offset added to the equilibrium moments (the uniform
+    off-equilibrium stress of the decay case), or None."""
+    if case.init != "decay":
+        return None
+    off = np.zeros(NF)
+    off[case.dim + 1:] = case.extra["delta"]
+    return off
 
 
 class Session:
@@ -69,12 +74,33 @@ class Session:
         """Equilibrium moments of the case's initial macroscopic fields [K, NF, Np]."""
         rho, u = self.case.macroscopic(self.nodes())
         q = equilibrium_moments(self.dim, rho, u, self.case.c).transpose(1, 0, 2).copy()
-        if self.case.init == "decay":
-            q[:, self.dim + 1:] += self.case.extra["delta"]
+        off = initial_offset(self.case, self.NF)
+        if off is not None:
+            q += off[None, :, None]
         return q
+
+    def set_initial_state(self, t0=0.0):
+        """The case's initial state, formed on the device from the macroscopic
+        fields at the nodes (gb_state_set_equilibrium)."""
+        rho, u = self.case.macroscopic(self.nodes())
+        L.gb_state_set_equilibrium(self.solver, rho, np.stack(u, axis=1), initial_offset(self.case, self.NF), t0)
 
     def set_state(self, q, t0=0.0):
         L.gb_state_set(self.solver, q, t0)
+
+    def energy(self, rho_inf=1.0):
+        """(E_K, epsilon_1, volume) at the current state."""
+        return L.gb_energy(self.solver, rho_inf)
+
+    def wall_force(self):
+        """(pressure force, viscous force) on the wall faces."""
+        return L.gb_wall_force(self.solver, self.dim)
+
+    def checkpoint(self) -> bytes:
+        return L.gb_checkpoint_save(self.solver)
+
+    def restore(self, data: bytes):
+        L.gb_checkpoint_load(self.solver, data)
 
     def get_state(self):
         return L.gb_state_get(self.solver, self.shape)

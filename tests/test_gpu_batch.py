@@ -48,8 +48,7 @@ class _Req:
         L.gb_set_motion(self.mesh, kind, p)
         self.K, self.Np, self.NF, _, _ = L.gb_mesh_sizes(self.mesh)
         self.solver = L.gb_solver_create(self.mesh, S.case_params(case, prec))
-        self.q0 = S.initial_state(case, self.mesh)
-        L.gb_state_set(self.solver, self.q0)
+        S.set_initial_state(case, self.mesh, self.solver)
 
     def state(self):
         return L.gb_state_get(self.solver, (self.K, self.NF, self.Np))
@@ -289,3 +288,60 @@ def test_batch_large_member_stepped_on_its_own():
     for r in reqs:
         r.close()
     L.gb_ctx_destroy(ctx)
+
+
+def _oracle_run(case, nsteps, **kw):
+    mesh = Mesh(case.dim, case.N, case.vx, case.etov, case.period, face_tag=case.face_tag)
+    mot = dict(case.motion)
+    o = Solver(mesh, Params(c=case.c, tau=case.tau, **kw), Motion(mot.pop("kind"), **mot))
+    X = o.node_coords()
+    rho, u = case.macroscopic(X)
+    o.set_state(gb.equilibrium(case.dim, rho, u, case.c).transpose(1, 0, 2).copy())
+    o.run(case.dt, nsteps)
+    return o
+
+
+def test_batch_fp32_member_matches_oracle():
+    """An FP32 member of a mixed batch (perturbation storage): velocity within
+    1e-5 relative of the FP64 oracle after 20 steps, density within 1e-6."""
+    case = make_case("C2_small", n=8)
+    ctx = L.gb_ctx_create(0, 0)
+    r = _Req(ctx, case, L.GB_FP32)
+    others = [_Req(ctx, make_case("C1", n=6, N=4), L.GB_FP32), _Req(ctx, make_case("C1", n=4, N=2), L.GB_FP32)]
+    b = L.gb_batch_create(ctx, BIG)
+    L.gb_batch_add(b, r.solver, case.dt, 20)
+    for o in others:
+        L.gb_batch_add(b, o.solver, o.case.dt, 9)
+    L.gb_batch_run(b, 20)
+    assert len(L.gb_batch_poll(b)) == 3
+    q, t, step = r.state()
+    o = _oracle_run(case, 20)
+    assert step == 20
+    ug = gb.velocity(2, q.transpose(1, 0, 2), case.c)
+    uo = gb.velocity(2, o.q.transpose(1, 0, 2), case.c)
+    assert np.linalg.norm(ug - uo) / np.linalg.norm(uo) < 1e-5
+    assert np.abs(q[:, 0] - o.q[:, 0]).max() < 1e-6
+    L.gb_batch_destroy(b)
+    for x in [r] + others:
+        x.close()
+    L.gb_ctx_destroy(ctx)
+
+
+def test_served_fp64_requests_match_oracle():
+    """The served loop with FP64 plunging-airfoil requests of orders 2-4 (walls,
+    far field, sponge): every request's final state matches the oracle element
+    by element within 1e-12 of each field's largest entry."""
+    specs = c5_requests(n=4, seed=5, mean_gap=0.003, nsteps=5, sizes=(4,), orders=(2, 3, 4))
+    reqs = [S.Request(index=s["index"], arrival=s["arrival"], case=c5_case(s), nsteps=s["nsteps"],
+                      precision=L.GB_FP64, keep_state=True) for s in specs]
+    srv = S.Server(BIG, steps_per_launch=2)
+    stats = srv.serve(reqs)
+    srv.close()
+    assert stats["completed"] == 4 and stats["failed"] == 0
+    for r in reqs:
+        c = r.case
+        q_inf = gb.equilibrium(2, np.array(1.0), [np.array(v) for v in c.extra["u"]], c.c)
+        o = _oracle_run(c, r.nsteps, q_inf=q_inf, sponge=c.extra["sponge"])
+        scale = np.abs(o.q).max(axis=(0, 2))
+        assert r.steps_done == r.nsteps
+        assert (np.abs(r.state - o.q).max(axis=(0, 2)) <= 1e-12 * np.maximum(scale, 1e-3)).all(), r.index

@@ -54,10 +54,10 @@ class _FakeLib:
     steps take simulated time proportional to the active members' size; no
     GPU, no arithmetic.  Records what the loop did."""
 
-    def __init__(self, sim, poisoned=()):
+    def __init__(self, sim, poisoned=(), unsupported=()):
         from paper_2607_00199_amd import _lib as L
         self.GbError, self.GB_FP32, self.make_params = L.GbError, L.GB_FP32, L.make_params
-        self.sim, self.poisoned = sim, set(poisoned)
+        self.sim, self.poisoned, self.unsupported = sim, set(poisoned), set(unsupported)
         self.max_used, self.admitted, self.live = 0, [], 0
 
     def gb_stream_create(self, device=0):
@@ -115,7 +115,15 @@ class _FakeLib:
     def gb_state_set(self, s, q, t0=0.0):
         pass
 
+    def gb_state_set_equilibrium(self, s, rho, u, offset=None, t0=0.0):
+        pass
+
+    def gb_equilibrium_moments(self, dim, c, rho, u):
+        return np.zeros((6 if dim == 2 else 10, np.size(rho)))
+
     def gb_batch_add(self, b, s, dt, nsteps):
+        if s["mesh"]["N"] in self.unsupported:
+            raise self.GbError(7, "the batched form is not built for this element shape and precision")
         need = 1010 * s["mesh"]["K"]
         if b["used"] + need > b["budget"]:
             raise self.GbError(8, "busy")
@@ -185,3 +193,21 @@ def test_served_loop_scheduling_with_a_fake_library(monkeypatch):
     order = [r.index for r in sorted((r for r in reqs if not r.rejected), key=lambda r: r.t_admit)]
     assert order == sorted(order)
     assert fake.live == 0                                # every mesh and solver released
+
+
+def test_served_loop_request_the_batch_refuses_fails_alone(monkeypatch):
+    """A request whose admission to the batch fails (a shape the batched
+    kernel is not built for) is reported as failed, its solver and mesh are
+    released, and every other request completes."""
+    from paper_2607_00199_amd import serve as S
+    from workloads import make_case
+    sim = [0.0]
+    cases = [make_case("C1", n=4, N=2), make_case("C1", n=4, N=5), make_case("C1", n=6, N=2)]
+    fake = _FakeLib(sim, unsupported={5})
+    monkeypatch.setattr(S, "L", fake)
+    srv = S.Server(1 << 40, steps_per_launch=2)
+    reqs = [S.Request(index=i, arrival=0.001 * i, case=c, nsteps=4) for i, c in enumerate(cases)]
+    stats = srv.serve(reqs, clock=lambda: sim[0], sleep=lambda dt: sim.__setitem__(0, sim[0] + dt))
+    assert stats["failed"] == 1 and reqs[1].error and "not built" in reqs[1].error
+    assert stats["completed"] == 2 and all(reqs[i].steps_done == 4 for i in (0, 2))
+    assert fake.live == 0
