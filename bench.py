@@ -155,10 +155,22 @@ def run_other(name: str, steps: int, warmup: int) -> dict:
             "frac": round(b / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def cpu_baseline(seconds_budget: float = 15.0):
+def host_cores() -> int:
+    """Host cores this process may use (its CPU affinity), at most 16 (the
+    host share of one GPU on a shared node)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(seconds_budget: float = 15.0, copies: int = 1):
     """Time the oracle (unchanged) on a bounded sample of the workload: the
     32 x 32 copy of the same configuration (2048 triangles, N = 4), as many
-    SARK-4 steps as fit the budget, in a child process pinned to one thread."""
+    SARK-4 steps as fit the budget, each copy in a child process pinned to one
+    thread.  With copies > 1, that many copies run at once on separate cores
+    (the oracle itself is serial) and the rate is their aggregate."""
     code = r"""
 import os, sys, time, json
 sys.path.insert(0, %r)
@@ -182,20 +194,29 @@ dof = case.K * s.mesh.ref.Np * 6
 print(json.dumps({"steps": n, "seconds": el, "K": case.K, "dof": dof, "gdof_stage_s": dof * 4 * n / el / 1e9}))
 """ % (ROOT, seconds_budget)
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                              text=True, env=env) for _ in range(copies)]
+    res = []
+    for pr in procs:
+        out, err = pr.communicate(timeout=600)
+        if pr.returncode != 0:
+            return {"error": err[-500:]}
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    agg = dict(res[0])
+    agg["copies"] = copies
+    agg["gdof_stage_s"] = sum(r["gdof_stage_s"] for r in res)
+    agg["steps"] = sum(r["steps"] for r in res)
+    return agg
 
 
-def run_served(args) -> dict:
+def run_served(args, requests=None, steps=None) -> dict:
     """The served form on the request mix: Poisson arrivals of plunging-airfoil
     requests of mixed size and order, continuous batching under an HBM budget;
     then every request timed alone (graph replay) for the serial reference."""
     from paper_2607_00199_amd import serve as S
     from workloads.configs import c5_case, c5_requests
 
-    specs = c5_requests(n=args.requests, seed=1, nsteps=args.served_steps)
+    specs = c5_requests(n=requests or args.requests, seed=1, nsteps=steps or args.served_steps)
     t0 = time.perf_counter()
     reqs = [S.Request(index=q["index"], arrival=q["arrival"], case=c5_case(q), nsteps=q["nsteps"]) for q in specs]
     print(f"served: {len(reqs)} request meshes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -254,6 +275,12 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=0.0, help="admission budget (0 = the whole device)")
     ap.add_argument("--steps-per-launch", type=int, default=5)
     ap.add_argument("--serial-steps", type=int, default=20)
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the bounded served run appended to the default line")
+    ap.add_argument("--served-requests-default", type=int, default=16,
+                    help="requests of the bounded served run on the default line")
+    ap.add_argument("--served-steps-default", type=int, default=1000,
+                    help="steps per request of the bounded served run on the default line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -302,6 +329,10 @@ def main():
                    "K": K, "N": case.N, "dof": r32["dof"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": ("profile: rocprofv3 FETCH_SIZE and WRITE_SIZE of this kernel source, "
+                                        "calibrated by kernels of known size, not measured in this run"
+                                        if traffic is not None else
+                                        "null: the kernel source changed since the counters were taken"),
                      "kernel": "stage_kernel<2,4,float,*> (4 stage kinds averaged)",
                      "bytes_per_launch": bytes_launch, "avg_launch_ms": round(r32["stage_avg_ms"], 5),
                      "launches": r32["stage_launches"],
@@ -328,6 +359,27 @@ def main():
                                "cores": 1, "kind": "oracle",
                                "sample": f"FP64 numpy oracle, 32x32-quad copy of the workload (K={cb.get('K')}, N=4), "
                                          f"{cb.get('steps')} SARK-4 steps in {cb.get('seconds', 0):.1f} s, one thread"}
+        ncores = host_cores()
+        ca = cpu_baseline(copies=ncores)
+        out["cpu_baseline_all_cores"] = {
+            "value": round(ca.get("gdof_stage_s", float("nan")), 6), "unit": "GDOF-stage/s", "cores": ncores,
+            "kind": "oracle",
+            "sample": f"{ncores} copies of the same sample at once, one per core (the oracle is serial), "
+                      f"{ca.get('steps')} SARK-4 steps in total in about {ca.get('seconds', 0):.1f} s"}
+    if not args.no_served:
+        sr = run_served(args, requests=args.served_requests_default, steps=args.served_steps_default)
+        st = sr["stats"]
+        out["served"] = {
+            "workload": f"{args.served_requests_default} plunging-airfoil requests of the served mix (Poisson "
+                        f"arrivals 20/s, O-grid K in [16384, 262144], N in 2..5, FP32), "
+                        f"{args.served_steps_default} SARK-4 steps each, continuous batching, whole-device budget",
+            "completed": st["completed"], "failed": st["failed"], "rejected": st["rejected"],
+            "latency_p50_s": st["latency_s"]["p50"], "latency_p99_s": st["latency_s"]["p99"],
+            "latency_max_s": st["latency_s"]["max"],
+            "aggregate_gdof_stage_s": round(st["gdof_stage_s"], 3),
+            "serial_plain_gdof_stage_s": round(sr["serial_gdof_stage_s"], 3),
+            "batched_vs_serial": round(st["gdof_stage_s"] / sr["serial_gdof_stage_s"], 3),
+            "makespan_s": round(st["makespan_s"], 3)}
     print(json.dumps(out))
 
 
