@@ -278,6 +278,21 @@ gb_status gb_rhs(gb_solver *solver, const double *q, double *F);
  * or while the solver is a member of a batch. */
 gb_status gb_energy(gb_solver *solver, double rho_inf, double out[3]);
 
+/* gb_energy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result bit for bit, with the reduction's
+ * partial sums in a fixed 64 KiB device array that the library holds on
+ * every device it runs on until the process ends, instead of a buffer the
+ * solver allocates on its first gb_energy call.  The call makes no device
+ * allocation or free.  That array takes at most 8192 doubles: one workgroup
+ * per 4 elements up to 4 per compute unit, 4 partial sums each, and the
+ * result; GB_ERR_ARG if the reduction would need more (not reached below
+ * 512 compute units).  All calls on one device share the array and it keeps
+ * the last call's contents (each call writes every entry it reads): calls
+ * that overlap in time on one device race, so issue them from one thread,
+ * one at a time.  Synchronises; errors as gb_energy. */
+gb_status gb_energy_noalloc(gb_solver *solver, double rho_inf, double out[3]);
+
 /* Force of the fluid on the body: the integral over every wall face
  * (GB_FACE_WALL) of p n (pressure, p = rho RT = c^2 rho) and of -sigma n
  * (viscous, sigma the deviatoric stress of Section 2: sigma_ab =

@@ -77,6 +77,7 @@ SIGNATURES = {
     "gb_checkpoint_save": (C.c_int, [_P, C.c_void_p, C.c_size_t]),
     "gb_checkpoint_load": (C.c_int, [_P, C.c_void_p, C.c_size_t]),
     "gb_energy": (C.c_int, [_P, C.c_double, _dp]),
+    "gb_energy_noalloc": (C.c_int, [_P, C.c_double, _dp]),
     "gb_wall_force": (C.c_int, [_P, _dp]),
     "gb_state_get": (C.c_int, [_P, _dp, _dp, C.POINTER(_i64)]),
     "gb_rhs": (C.c_int, [_P, _dp, _dp]),
@@ -286,6 +287,13 @@ def gb_energy(solver, rho_inf: float = 1.0):
     """(E_K, epsilon_1 = -dE_K/dt, domain volume) at the current state."""
     out = np.zeros(3)
     _check(load().gb_energy(solver, rho_inf, _dptr(out)))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def gb_energy_noalloc(solver, rho_inf: float = 1.0):
+    """gb_energy without device allocation (fixed library scratch)."""
+    out = np.zeros(3)
+    _check(load().gb_energy_noalloc(solver, rho_inf, _dptr(out)))
     return float(out[0]), float(out[1]), float(out[2])
 
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -51,12 +52,42 @@ struct DevBuf {
 
 }  // namespace
 
+// Device scratch for the allocation-free energy diagnostic: per-workgroup
+// partial sums and the result.  Every device holds its own copy for the life
+// of the process; host code reaches it only through the address returned by
+// hipGetSymbolAddress for that device (kept in scratch_addr below).
+constexpr size_t kScratchDoubles = 8192;   // 64 KiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 struct gb_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cu = 256;
     size_t max_lds = 65536;
+    double *scratch = nullptr;      // this device's copy of the scratch array
 };
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_addr;   // device -> address of its scratch
+
+// Address of the scratch array on `device` (current device), looked up once
+// per device.
+hipError_t scratch_addr(int device, double **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = static_cast<double *>(p);
+    *out = static_cast<double *>(p);
+    return hipSuccess;
+}
+}  // namespace
 
 struct gb_mesh {
     gb_ctx *ctx = nullptr;
@@ -764,6 +795,7 @@ gb_status gb_ctx_create(int device, void *stream, gb_ctx **out) {
     GB_HIP(hipGetDeviceProperties(&prop, device));
     c->num_cu = prop.multiProcessorCount;
     c->max_lds = prop.sharedMemPerBlock;
+    GB_HIP(scratch_addr(device, &c->scratch));
     *out = c.release();
     return GB_OK;
 }
@@ -1417,6 +1449,31 @@ gb_status gb_energy(gb_solver *s, double rho_inf, double out[3]) {
     if (s->diag.bytes < need && s->diag.alloc(need) != hipSuccess) return fail(GB_ERR_OOM, "energy reduction buffer");
     hipStream_t st = s->mesh->ctx->stream;
     double *partial = s->diag.as<double>();
+    double *result = partial + size_t(grid) * gbd::kDiagSums;
+    r = enqueue_energy(s, L, rho_inf, partial, result, st);
+    if (r != GB_OK) return r;
+    GB_HIP(hipMemcpyAsync(out, result, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    GB_HIP(hipStreamSynchronize(st));
+    return check_error_flag(s);
+}
+
+gb_status gb_energy_noalloc(gb_solver *s, double rho_inf, double out[3]) {
+    if (!s || !out) return fail(GB_ERR_ARG, "NULL argument");
+    if (!(rho_inf > 0.0)) return fail(GB_ERR_ARG, "rho_inf must be positive");
+    Launcher L;
+    gb_status r = check_diag_call(s, L);
+    if (r != GB_OK) return r;
+    const int grid = energy_grid(s);
+    const size_t need = size_t(grid) * gbd::kDiagSums + 4;
+    if (need > kScratchDoubles)
+        return fail(GB_ERR_ARG, "the reduction needs " + std::to_string(need) + " doubles of scratch, more than the " +
+                                    std::to_string(kScratchDoubles) + " of the allocation-free form");
+    gb_ctx *ctx = s->mesh->ctx;
+    if (!ctx->scratch) return fail(GB_ERR_STATE, "no scratch address for this device");
+    hipStream_t st = ctx->stream;
+    // every workgroup writes all of its partial sums and the final pass
+    // writes the whole result, so nothing has to be cleared first
+    double *partial = ctx->scratch;
     double *result = partial + size_t(grid) * gbd::kDiagSums;
     r = enqueue_energy(s, L, rho_inf, partial, result, st);
     if (r != GB_OK) return r;
