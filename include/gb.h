@@ -181,6 +181,25 @@ gb_status gb_mesh_sizes(const gb_mesh *mesh, int64_t *K, int *Np, int *NF, int *
 gb_status gb_ref_operator(int dim, int N, int cubature_degree, int which, double *out,
                           int64_t capacity, int64_t *n_out);
 
+/* Host-only checks (no device work), for validating inputs and the library's
+ * own table construction without a GPU:
+ *   gb_check_mesh_tables builds the connectivity and the blocked trace map
+ *   exactly as gb_mesh_create does and checks them: vertex ids in range,
+ *   every trace-map entry a boundary code or a face node of another element,
+ *   the map an involution on matched faces, the blocked copy equal to the
+ *   flat one with padding elsewhere.  GB_ERR_MESH with the first violation.
+ *   gb_check_batch_layout builds the request-table layout of a batched launch
+ *   class of nmembers meshes (K[i] elements, nv[i] vertices) with the buffer
+ *   sizes gb_mesh_create / gb_solver_create allocate and checks it as
+ *   gb_batch_run does before every table upload: buffers cover what the
+ *   kernel addresses, group offsets are the running sums, counts within
+ *   limits, and the dynamic LDS of the launch (written to *lds_bytes) within
+ *   lds_limit.  GB_ERR_STATE with the first violation. */
+gb_status gb_check_mesh_tables(int dim, int N, int64_t nv, const double *vx, int64_t K, const int32_t *etov,
+                               const double *period, const int8_t *face_tag);
+gb_status gb_check_batch_layout(int dim, int N, int precision, int cubature_degree, int nmembers, const int64_t *K,
+                                const int64_t *nv, size_t lds_limit, size_t *lds_bytes);
+
 /* Current node coordinates [K][dim][Np] (host output). */
 gb_status gb_mesh_nodes(const gb_mesh *mesh, double *xyz);
 

@@ -63,6 +63,10 @@ SIGNATURES = {
     "gb_mesh_sizes": (C.c_int, [_P, C.POINTER(_i64), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                 C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "gb_ref_operator": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _i64, C.POINTER(_i64)]),
+    "gb_check_mesh_tables": (C.c_int, [C.c_int, C.c_int, _i64, _dp, _i64, C.POINTER(C.c_int32), _dp,
+                                       C.POINTER(C.c_int8)]),
+    "gb_check_batch_layout": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_i64),
+                                        C.POINTER(_i64), C.c_size_t, C.POINTER(C.c_size_t)]),
     "gb_mesh_nodes": (C.c_int, [_P, _dp]),
     "gb_mesh_vertices": (C.c_int, [_P, _dp]),
     "gb_set_motion": (C.c_int, [_P, C.POINTER(gb_motion)]),
@@ -174,6 +178,30 @@ def gb_mesh_create(ctx, dim: int, N: int, vx, etov, period=None, face_tag=None):
                                  None if tag is None else tag.ctypes.data_as(C.POINTER(C.c_int8)),
                                  C.byref(out)))
     return out
+
+
+def gb_check_mesh_tables(dim: int, N: int, vx, etov, period=None, face_tag=None):
+    """Host-only check of the library's connectivity and trace map for a mesh."""
+    vx = _f64(vx)
+    etov = np.ascontiguousarray(etov, dtype=np.int32)
+    per = None if period is None else _f64(period)
+    tag = None if face_tag is None else np.ascontiguousarray(face_tag, dtype=np.int8)
+    _check(load().gb_check_mesh_tables(dim, N, vx.shape[0], _dptr(vx), etov.shape[0],
+                                       etov.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       None if per is None else _dptr(per),
+                                       None if tag is None else tag.ctypes.data_as(C.POINTER(C.c_int8))))
+
+
+def gb_check_batch_layout(dim: int, N: int, precision: int, K, nv, lds_limit: int, cubature_degree: int = 0) -> int:
+    """Host-only check of a batched launch class's table layout; returns the
+    dynamic LDS bytes of the launch."""
+    K = np.ascontiguousarray(K, dtype=np.int64)
+    nv = np.ascontiguousarray(nv, dtype=np.int64)
+    out = C.c_size_t()
+    _check(load().gb_check_batch_layout(dim, N, precision, cubature_degree, K.size,
+                                        K.ctypes.data_as(C.POINTER(_i64)), nv.ctypes.data_as(C.POINTER(_i64)),
+                                        int(lds_limit), C.byref(out)))
+    return out.value
 
 
 def gb_mesh_destroy(mesh):

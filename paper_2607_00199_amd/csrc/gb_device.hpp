@@ -148,12 +148,33 @@ __device__ __forceinline__ void sub_cMd(T c, const T *g, T *out) {
     }
 }
 
+// Reciprocal and reciprocal square root from the hardware approximations
+// (v_rcp / v_rsq) refined by Newton-Raphson steps: one step in FP32 (the
+// approximation is within 1 ulp), two in FP64 (each step doubles the correct
+// bits of the approximation); a handful of instructions instead of the
+// correctly rounded division and square root sequences.
+__device__ __forceinline__ float rcp_nr(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    const double h = 0.5 * x;
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return fma(y, fma(-h * y, y, 0.5), y);
+}
+
 // Nonlinear relaxation source Ntilde (Section 4) for the stress fields,
 // given density and momentum at a point: m_a m_b / (tau rho) off the
 // diagonal, m_a^2 / (sqrt2 tau rho) on it.
 template <int DIM, typename T>
 __device__ __forceinline__ void ntilde(T rho, const T *m, T inv_tau, T *out) {
-    const T k = inv_tau * (T(1) / rho);
+    const T k = inv_tau * rcp_nr(rho);
     const T kd = k * T(1.0 / kSqrt2);
     if constexpr (DIM == 2) {
         out[0] = k * m[0] * m[1];

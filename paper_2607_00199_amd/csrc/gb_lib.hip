@@ -191,6 +191,7 @@ void fill_kconst(gbd::KConst<T> &k, const gb_solver *s, double dt) {
     fill_coef(k.cf[0], gbh::sark_coefficients(0.0), dt);
     fill_coef(k.cf[1], gbh::sark_coefficients(-dt / s->prm.tau), dt);
     k.c = T(s->prm.c);
+    k.inv_c = T(1.0 / s->prm.c);
     k.inv_tau = T(1.0 / s->prm.tau);
     const double rho0 = s->prm.precision == GB_FP32 ? s->prm.rho0 : 0.0;
     k.rho0 = T(rho0);
@@ -504,6 +505,7 @@ template <typename T>
 gb_status upload_class_table(gb_batch *b, gb_batch::Class &c) {
     std::vector<gbd::BatchEntry<T>> ent(c.idx.size());
     std::vector<int32_t> gb(c.idx.size());
+    std::vector<gbh::BatchMemberLayout> lay(c.idx.size());
     int64_t g = 0;
     for (size_t i = 0; i < c.idx.size(); ++i) {
         const gb_batch::Member &mb = b->members[size_t(c.idx[i])];
@@ -512,8 +514,22 @@ gb_status upload_class_table(gb_batch *b, gb_batch::Class &c) {
         ent[i] = make_entry<T>(s, mb.target);
         gb[i] = int32_t(g);
         g += (m->K + 15) / 16;
+        lay[i].K = m->K;
+        lay[i].nv = m->nv;
+        lay[i].etov_bytes = m->d_etov.bytes;
+        lay[i].vstage_bytes = s->vstage.bytes;
+        lay[i].wstage_bytes = s->wstage.bytes;
+        lay[i].vmap_bytes = m->d_vmapP.bytes;
+        lay[i].state_bytes = std::min(std::min(s->Q.bytes, s->A.bytes), std::min(s->B.bytes, s->G.bytes));
     }
     if (g >= (int64_t(1) << 31)) return fail(GB_ERR_UNSUPPORTED, "too many element groups in one class");
+    {
+        const gb_solver *s0 = b->members[size_t(c.idx[0])].s;
+        const std::string bad =
+            gbh::check_batch_class(c.dim, s0->ref.Np, s0->NF, s0->ref.Nfaces * s0->ref.Nfp, sizeof(T), lay, gb, g,
+                                   gbd::kMaxBatch, c.shape.batch_lds(c.Nc, int(c.idx.size())), b->ctx->max_lds);
+        if (!bad.empty()) return fail(GB_ERR_STATE, "batch table check: " + bad);
+    }
     c.total = g;
     if (c.ent.alloc(ent.size() * sizeof(ent[0])) != hipSuccess || c.gbeg.alloc(gb.size() * sizeof(int32_t)) != hipSuccess)
         return fail(GB_ERR_OOM, "batch request table");
@@ -859,6 +875,65 @@ gb_status gb_ref_operator(int dim, int N, int cubature_degree, int which, double
     return GB_OK;
 }
 
+gb_status gb_check_mesh_tables(int dim, int N, int64_t nv, const double *vx, int64_t K, const int32_t *etov,
+                               const double *period, const int8_t *face_tag) {
+    if (!vx || !etov) return fail(GB_ERR_ARG, "NULL argument");
+    if (dim != 2 && dim != 3) return fail(GB_ERR_ARG, "dim must be 2 or 3");
+    if (!supported(dim, N)) return fail(GB_ERR_UNSUPPORTED, "polynomial order not built for this dimension");
+    if (nv <= 0 || K <= 0) return fail(GB_ERR_ARG, "empty mesh");
+    try {
+        const gbh::RefElement ref = gbh::build_ref_element(dim, N, 0);
+        std::string err;
+        const gbh::Connectivity conn = gbh::build_connectivity(ref, nv, vx, K, etov, period, face_tag, err);
+        if (!err.empty()) return fail(GB_ERR_MESH, err);
+        const std::vector<int32_t> blk = gbh::blocked_trace_map(ref, K, conn);
+        const std::string bad = gbh::check_mesh_tables(ref, nv, K, etov, conn, blk);
+        if (!bad.empty()) return fail(GB_ERR_MESH, bad);
+    } catch (const std::exception &ex) {
+        return fail(GB_ERR_ARG, ex.what());
+    }
+    return GB_OK;
+}
+
+gb_status gb_check_batch_layout(int dim, int N, int precision, int cubature_degree, int nmembers, const int64_t *K,
+                                const int64_t *nv, size_t lds_limit, size_t *lds_bytes) {
+    if (!K || !nv || !lds_bytes || nmembers <= 0) return fail(GB_ERR_ARG, "NULL argument or no member");
+    Launcher L;
+    if (!get_launcher(dim, N, precision, L)) return fail(GB_ERR_UNSUPPORTED, "no kernel for this shape");
+    try {
+        const gbh::RefElement ref = gbh::build_ref_element(dim, N, cubature_degree);
+        const size_t es = precision == GB_FP32 ? 4 : 8;
+        const int NF = n_fields(dim), NFT = ref.Nfaces * ref.Nfp, slots = (NFT + 3) / 4 * 4;
+        std::vector<gbh::BatchMemberLayout> lay(static_cast<size_t>(nmembers));
+        std::vector<int32_t> gbeg(static_cast<size_t>(nmembers));
+        int64_t g = 0;
+        for (int i = 0; i < nmembers; ++i) {
+            // the buffer sizes gb_mesh_create and gb_solver_create allocate
+            gbh::BatchMemberLayout &b = lay[size_t(i)];
+            b.K = K[i];
+            b.nv = nv[i];
+            const int64_t groups = (K[i] + 15) / 16;
+            b.etov_bytes = size_t(K[i]) * (dim + 1) * sizeof(int32_t);
+            b.vstage_bytes = 5 * size_t(nv[i]) * dim * sizeof(double);
+            b.wstage_bytes = 4 * size_t(nv[i]) * dim * sizeof(double);
+            b.vmap_bytes = size_t(groups) * slots * 16 * sizeof(int32_t);
+            b.state_bytes = size_t(groups) * 16 * NF * ref.Np * es;
+            gbeg[size_t(i)] = int32_t(g);
+            g += groups;
+        }
+        // dynamic LDS of the batched launch: the single-mesh kernel's
+        // (operator fragments, slot table, staged blocks) plus the group offsets
+        const size_t lds = (L.lds(ref.Nc) + 15) / 16 * 16 + size_t(nmembers) * sizeof(int32_t);
+        *lds_bytes = lds;
+        const std::string bad =
+            gbh::check_batch_class(dim, ref.Np, NF, NFT, es, lay, gbeg, g, gbd::kMaxBatch, lds, lds_limit);
+        if (!bad.empty()) return fail(GB_ERR_STATE, bad);
+    } catch (const std::exception &ex) {
+        return fail(GB_ERR_ARG, ex.what());
+    }
+    return GB_OK;
+}
+
 gb_status gb_mesh_create(gb_ctx *ctx, int dim, int N, int64_t nv, const double *vx, int64_t K, const int32_t *etov,
                          const double *period, const int8_t *face_tag, gb_mesh **out) {
     if (!ctx || !vx || !etov || !out) return fail(GB_ERR_ARG, "NULL argument");
@@ -906,13 +981,11 @@ gb_status gb_mesh_create(gb_ctx *ctx, int dim, int N, int64_t nv, const double *
     GB_HIP(hipMemcpy(m->d_x.p, vx, m->d_x.bytes, hipMemcpyHostToDevice));
     {
         // blocked trace map [K/16][slots][16] (slots = face nodes rounded up to
-        // a multiple of 4); -3 marks padding
+        // a multiple of 4; -3 marks padding), checked against the flat map
         const int NFT = m->ref.Nfaces * m->ref.Nfp;
-        const int slots = (NFT + 3) / 4 * 4;
-        const int64_t G = (K + 15) / 16;
-        std::vector<int32_t> blk(size_t(G) * slots * 16, -3);
-        for (int64_t e = 0; e < K; ++e)
-            for (int mm = 0; mm < NFT; ++mm) blk[((e >> 4) * slots + mm) * 16 + (e & 15)] = m->conn.vmapP[e * NFT + mm];
+        const std::vector<int32_t> blk = gbh::blocked_trace_map(m->ref, K, m->conn);
+        const std::string bad = gbh::check_mesh_tables(m->ref, nv, K, etov, m->conn, blk);
+        if (!bad.empty()) return fail(GB_ERR_MESH, bad);
         if (m->d_vmapP.alloc(blk.size() * sizeof(int32_t)) != hipSuccess) return fail(GB_ERR_OOM, "vmapP");
         GB_HIP(hipMemcpy(m->d_vmapP.p, blk.data(), m->d_vmapP.bytes, hipMemcpyHostToDevice));
         // wall faces (trace map -1) for the force integral, the face node

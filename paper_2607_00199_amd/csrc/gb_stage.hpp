@@ -39,7 +39,7 @@ struct StageCoef {
 template <typename T>
 struct KConst {
     StageCoef<T> cf[2];  // [0] density/momentum (no relaxation), [1] stresses
-    T c, inv_tau, rho0;
+    T c, inv_c, inv_tau, rho0;
     int flux_mode;       // 0 split, 1 relative
     T fluxV[25];         // relative mode, row p: coefficients of g -> power p of M_n
     T q_inf[10];

@@ -690,6 +690,89 @@ Connectivity build_connectivity(const RefElement &R, int64_t nv, const double *v
     return C;
 }
 
+// ---------------------------------------------------------------- table checks
+
+std::vector<int32_t> blocked_trace_map(const RefElement &ref, int64_t K, const Connectivity &conn) {
+    const int NFT = ref.Nfaces * ref.Nfp;
+    const int slots = (NFT + 3) / 4 * 4;
+    const int64_t G = (K + 15) / 16;
+    std::vector<int32_t> blk(size_t(G) * slots * 16, -3);
+    for (int64_t e = 0; e < K; ++e)
+        for (int m = 0; m < NFT; ++m) blk[((e >> 4) * slots + m) * 16 + (e & 15)] = conn.vmapP[e * NFT + m];
+    return blk;
+}
+
+std::string check_mesh_tables(const RefElement &ref, int64_t nv, int64_t K, const int32_t *etov,
+                              const Connectivity &conn, const std::vector<int32_t> &blocked) {
+    const int Np = ref.Np, Nf = ref.Nfaces, Nfp = ref.Nfp, NFT = Nf * Nfp, nvert = ref.dim + 1;
+    const int slots = (NFT + 3) / 4 * 4;
+    const int64_t G = (K + 15) / 16;
+    if (int64_t(conn.vmapP.size()) != K * NFT) return "trace map has the wrong size";
+    if (int64_t(blocked.size()) != G * slots * 16) return "blocked trace map has the wrong size";
+    for (int64_t e = 0; e < K; ++e)
+        for (int v = 0; v < nvert; ++v) {
+            const int32_t gv = etov[e * nvert + v];
+            if (gv < 0 || gv >= nv) return "vertex id out of range at element " + std::to_string(e);
+        }
+    // node -> (face slot) of each element, for the involution check
+    std::vector<int> slot_of_node(size_t(Nf) * Np, -1);
+    for (int f = 0; f < Nf; ++f)
+        for (int m = 0; m < Nfp; ++m) slot_of_node[size_t(f) * Np + ref.fmask[f * Nfp + m]] = f * Nfp + m;
+    for (int64_t e = 0; e < K; ++e)
+        for (int f = 0; f < Nf; ++f)
+            for (int m = 0; m < Nfp; ++m) {
+                const int32_t idx = conn.vmapP[(e * Nf + f) * Nfp + m];
+                if (idx == -1 || idx == -2) continue;
+                if (idx < 0 || int64_t(idx) >= K * Np)
+                    return "trace-map entry out of range at element " + std::to_string(e);
+                const int64_t e2 = idx / Np;
+                const int j2 = int(idx - e2 * Np);
+                // the partner's node lies on the face that points back at e
+                int back = -1;
+                for (int ff = 0; ff < Nf; ++ff)
+                    if (conn.etoe[e2 * Nf + ff] == e && slot_of_node[size_t(ff) * Np + j2] >= 0) {
+                        const int m2 = slot_of_node[size_t(ff) * Np + j2];
+                        if (conn.vmapP[e2 * NFT + m2] == int32_t(e * Np + ref.fmask[f * Nfp + m])) back = m2;
+                    }
+                if (back < 0) return "trace map is not an involution at element " + std::to_string(e);
+            }
+    for (int64_t g = 0; g < G; ++g)
+        for (int m = 0; m < slots; ++m)
+            for (int l = 0; l < 16; ++l) {
+                const int64_t e = g * 16 + l;
+                const int32_t got = blocked[(g * slots + m) * 16 + l];
+                const int32_t want = (e < K && m < NFT) ? conn.vmapP[e * NFT + m] : -3;
+                if (got != want) return "blocked trace map differs from the flat one at group " + std::to_string(g);
+            }
+    return std::string();
+}
+
+std::string check_batch_class(int dim, int Np, int NF, int NFT, size_t elem_bytes,
+                              const std::vector<BatchMemberLayout> &members, const std::vector<int32_t> &group_begin,
+                              int64_t total_groups, int max_members, size_t lds_bytes, size_t lds_limit) {
+    if (members.empty()) return "empty class";
+    if (int(members.size()) > max_members) return "more members than the request table holds";
+    if (group_begin.size() != members.size()) return "group offsets and members differ in number";
+    const int slots = (NFT + 3) / 4 * 4;
+    int64_t g = 0;
+    for (size_t i = 0; i < members.size(); ++i) {
+        const BatchMemberLayout &b = members[i];
+        const int64_t groups = (b.K + 15) / 16;
+        if (b.K <= 0 || b.nv <= 0) return "member " + std::to_string(i) + " is empty";
+        if (group_begin[i] != g) return "group offset of member " + std::to_string(i) + " is not the running sum";
+        if (b.etov_bytes < size_t(b.K) * (dim + 1) * sizeof(int32_t)) return "vertex-id buffer too small";
+        if (b.vstage_bytes < 5 * size_t(b.nv) * dim * sizeof(double)) return "stage-position buffer too small";
+        if (b.wstage_bytes < 4 * size_t(b.nv) * dim * sizeof(double)) return "stage-velocity buffer too small";
+        if (b.vmap_bytes < size_t(groups) * slots * 16 * sizeof(int32_t)) return "trace-map buffer too small";
+        if (b.state_bytes < size_t(groups) * 16 * NF * Np * elem_bytes) return "state buffer too small";
+        g += groups;
+    }
+    if (g != total_groups) return "total group count differs from the members' sum";
+    if (total_groups >= (int64_t(1) << 31)) return "too many element groups in one class";
+    if (lds_bytes > lds_limit) return "dynamic LDS of the launch exceeds the limit set for the kernel";
+    return std::string();
+}
+
 // ---------------------------------------------------------------- SARK-4
 
 // phi_k(z) = sum_m z^m / (m+k)!  (k = 1..3): power series for |z| < 1, the

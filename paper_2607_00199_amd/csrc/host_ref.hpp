@@ -57,6 +57,36 @@ Connectivity build_connectivity(const RefElement &ref, int64_t nv, const double 
                                 const int32_t *etov, const double *period, const int8_t *face_tag,
                                 std::string &err);
 
+// Trace map in the device's blocked layout [ceil(K/16)][slots][16] (slots =
+// Nfaces*Nfp rounded up to 4): the exterior node of face node m of element e,
+// or -1 (wall), -2 (far field), -3 (padding of the last group or slot).
+std::vector<int32_t> blocked_trace_map(const RefElement &ref, int64_t K, const Connectivity &conn);
+
+// Consistency of the device tables of a mesh, checked on the host: every
+// trace-map entry is a boundary code or a node of another element's face,
+// the map is an involution on matched faces, the blocked copy equals the
+// flat one with padding where no element or slot exists, and every element's
+// vertex ids are in range.  Returns an empty string or the first violation.
+std::string check_mesh_tables(const RefElement &ref, int64_t nv, int64_t K, const int32_t *etov,
+                              const Connectivity &conn, const std::vector<int32_t> &blocked);
+
+// One member of a batched launch class, as the request table describes it:
+// its element and vertex counts and the sizes in bytes of the device buffers
+// its table entry points to.
+struct BatchMemberLayout {
+    int64_t K = 0, nv = 0;
+    size_t etov_bytes = 0, vstage_bytes = 0, wstage_bytes = 0, vmap_bytes = 0, state_bytes = 0;
+};
+
+// Checks of a batched launch class before its table is uploaded: every
+// buffer covers what the kernel addresses for that member (elements padded to
+// whole groups of 16), the group offsets start at 0 and grow by each member's
+// group count, the total stays below 2^31 groups, the member count within
+// max_members, and the dynamic LDS the launch asks for within lds_limit.
+std::string check_batch_class(int dim, int Np, int NF, int NFT, size_t elem_bytes,
+                              const std::vector<BatchMemberLayout> &members, const std::vector<int32_t> &group_begin,
+                              int64_t total_groups, int max_members, size_t lds_bytes, size_t lds_limit);
+
 // SARK-4 coefficients for one field class with gamma = -dt * rate.
 struct SarkCoef {
     double E[5];      // exp(c_i gamma) multiplying q_n: stages 0..3, final
