@@ -364,7 +364,9 @@ gb_status gb_solver_stage_time_by_kind(gb_solver *solver, double *avg_ms4);
  * gb_batch_run after a change.  The launch grid of each class is chosen by
  * timing the first stage at several grids the first time the class runs
  * (stage 0 at a step boundary only overwrites a buffer the next step
- * recomputes, so the tuning leaves every member's state unchanged).
+ * recomputes, so the tuning leaves every member's state unchanged); the
+ * tile tried covers workgroups per CU, wavefronts per workgroup and the
+ * dealing of groups to workgroups (gb_batch_class_tile, gb_tune_cache_*).
  * ------------------------------------------------------------------------ */
 
 /* Create a batch on ctx's stream with an admission budget in bytes of device
@@ -395,6 +397,13 @@ gb_status gb_batch_poll(gb_batch *batch, uint64_t *done, int capacity, int *n_do
 /* Members, budget in use, and budget. */
 gb_status gb_batch_info(const gb_batch *batch, int *active, size_t *used_bytes, size_t *budget);
 
+/* Members large enough to be stepped on their own run on up to `streams`
+ * streams at once (library-owned, default priority), so that the last
+ * workgroups of one member's kernels overlap another's; 1 (default) steps
+ * them in turn on the batch's stream.  Results do not depend on it.  Waits
+ * for the batch's queued work. */
+gb_status gb_batch_set_concurrency(gb_batch *batch, int streams);
+
 /* Enable (default) or disable the launch-grid tuning of new classes. */
 gb_status gb_batch_set_autotune(gb_batch *batch, int enable);
 
@@ -406,6 +415,24 @@ gb_status gb_batch_set_autotune(gb_batch *batch, int enable);
  * stage. */
 gb_status gb_batch_class_count(const gb_batch *batch, int *n);
 gb_status gb_batch_class_info(const gb_batch *batch, int i, int64_t *info7);
+
+/* Launch tile of class i: tile3 = {workgroups, wavefronts per workgroup (4,
+ * or 8 for the kernels that run two wavefronts per SIMD), group dealing (0 =
+ * contiguous ranges per workgroup, 1 = blocks of one group per wavefront
+ * dealt round robin)}.  The tile does not change any member's result. */
+gb_status gb_batch_class_tile(const gb_batch *batch, int i, int64_t *tile3);
+
+/* Launch-tile cache of the autotuner.  The first run of a class (same device
+ * architecture, dimension, order, precision, cubature size, solo or shared,
+ * and power-of-two bucket of its element groups) times stage 0 for every
+ * candidate tile (1, 2, 4, 8, 16 workgroups per CU; 4 or 8 wavefronts per
+ * workgroup; ranges or round-robin dealing) and keeps the fastest in a
+ * process-wide cache; later batches reuse it without timing.  The cache can
+ * be saved to a text file and loaded in another process (entries merge,
+ * loaded ones win); a malformed file is refused with GB_ERR_ARG. */
+gb_status gb_tune_cache_save(const char *path);
+gb_status gb_tune_cache_load(const char *path, int *entries);
+void gb_tune_cache_clear(void);
 
 #ifdef __cplusplus
 }

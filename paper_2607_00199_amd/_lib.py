@@ -98,8 +98,13 @@ SIGNATURES = {
     "gb_batch_poll": (C.c_int, [_P, C.POINTER(C.c_uint64), C.c_int, C.POINTER(C.c_int)]),
     "gb_batch_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "gb_batch_set_autotune": (C.c_int, [_P, C.c_int]),
+    "gb_batch_set_concurrency": (C.c_int, [_P, C.c_int]),
     "gb_batch_class_count": (C.c_int, [_P, C.POINTER(C.c_int)]),
     "gb_batch_class_info": (C.c_int, [_P, C.c_int, C.POINTER(_i64)]),
+    "gb_batch_class_tile": (C.c_int, [_P, C.c_int, C.POINTER(_i64)]),
+    "gb_tune_cache_save": (C.c_int, [C.c_char_p]),
+    "gb_tune_cache_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_int)]),
+    "gb_tune_cache_clear": (None, []),
 }
 
 _lib = None
@@ -418,6 +423,10 @@ def gb_batch_set_autotune(batch, enable: bool):
     _check(load().gb_batch_set_autotune(batch, 1 if enable else 0))
 
 
+def gb_batch_set_concurrency(batch, streams: int):
+    _check(load().gb_batch_set_concurrency(batch, int(streams)))
+
+
 def gb_batch_class_count(batch) -> int:
     n = C.c_int()
     _check(load().gb_batch_class_count(batch, C.byref(n)))
@@ -428,3 +437,23 @@ def gb_batch_class_info(batch, i: int) -> dict:
     out = (_i64 * 7)()
     _check(load().gb_batch_class_info(batch, i, out))
     return dict(zip(("dim", "N", "precision", "members", "groups", "grid", "solo"), (int(v) for v in out)))
+
+
+def gb_batch_class_tile(batch, i: int) -> dict:
+    out = (_i64 * 3)()
+    _check(load().gb_batch_class_tile(batch, i, out))
+    return dict(zip(("grid", "waves", "interleave"), (int(v) for v in out)))
+
+
+def gb_tune_cache_save(path: str):
+    _check(load().gb_tune_cache_save(path.encode()))
+
+
+def gb_tune_cache_load(path: str) -> int:
+    n = C.c_int()
+    _check(load().gb_tune_cache_load(path.encode(), C.byref(n)))
+    return n.value
+
+
+def gb_tune_cache_clear():
+    load().gb_tune_cache_clear()

@@ -38,7 +38,9 @@ struct BatchLaunch {
     int64_t total = 0;                 // element groups over all entries
     int Nc = 0;
     int grid = 1;                      // workgroups to aim for
-    size_t lds = 0;                    // dynamic LDS bytes (batch_lds of nreq)
+    int waves = kWaves;                // wavefronts per workgroup (batch_waves)
+    bool interleave = false;           // groups dealt to workgroups round robin instead of in ranges
+    size_t lds = 0;                    // dynamic LDS bytes (batch_lds of nreq and waves)
     const void *ops = nullptr;
     const int32_t *fmask = nullptr;
 };
@@ -49,7 +51,8 @@ struct ShapeEntry {
     int (*ops_total)(int Nc);
     // batched form; null for the shapes it is not built for
     hipError_t (*batch_stage)(const BatchLaunch &, int kind, hipStream_t);
-    size_t (*batch_lds)(int Nc, int nreq);
+    size_t (*batch_lds)(int Nc, int nreq, int waves);
+    int batch_waves_max;
     // raises the dynamic-LDS limit of the batched kernels (outside capture)
     hipError_t (*batch_allow_lds)(size_t bytes);
     // largest per-lane scratch of the batched kernels (0 expected)
@@ -111,17 +114,24 @@ hipError_t launch_stage_batch(const BatchLaunch &L, int kind, hipStream_t st) {
     b.Nc = L.Nc;
     b.ops = static_cast<const T *>(L.ops);
     b.fmask = L.fmask;
-    int grid = int(std::min<int64_t>(L.grid, (L.total + kWaves - 1) / kWaves));
+    const int waves = L.waves;
+    int grid = int(std::min<int64_t>(L.grid, (L.total + waves - 1) / waves));
     if (grid < 1) grid = 1;
     if (grid >= 8) grid = grid / 8 * 8;
     b.chunk = int((L.total + grid - 1) / grid);
     grid = int((L.total + b.chunk - 1) / b.chunk);
     if (grid >= 8 && grid % 8) grid = (grid + 7) / 8 * 8;
+    b.stride = 0;
+    if (L.interleave) {
+        // every workgroup starts at its own index and strides by the grid
+        b.chunk = 1;
+        b.stride = grid;
+    }
     using K0 = decltype(&stage_batch_kernel<DIM, N, T, 0>);
     const K0 fns[5] = {&stage_batch_kernel<DIM, N, T, 0>, &stage_batch_kernel<DIM, N, T, 1>,
                        &stage_batch_kernel<DIM, N, T, 2>, &stage_batch_kernel<DIM, N, T, 3>,
                        &stage_batch_kernel<DIM, N, T, 4>};
-    hipLaunchKernelGGL(fns[kind < 4 ? kind : 4], dim3(grid), dim3(64 * kWaves), L.lds, st, b, b.ent);
+    hipLaunchKernelGGL(fns[kind < 4 ? kind : 4], dim3(grid), dim3(64 * waves), L.lds, st, b, b.ent);
     return hipGetLastError();
 }
 
@@ -161,7 +171,7 @@ hipError_t batch_scratch(size_t *bytes) {
 }
 
 template <int DIM, int N, typename T>
-size_t stage_batch_lds(int Nc, int nreq) { return batch_lds_bytes<DIM, N, T>((Nc + 15) / 16, nreq); }
+size_t stage_batch_lds(int Nc, int nreq, int waves) { return batch_lds_bytes<DIM, N, T>((Nc + 15) / 16, nreq, waves); }
 
 template <int DIM, int N, typename T>
 size_t stage_lds(int Nc) { return mfma_lds_bytes<DIM, N, T>((Nc + 15) / 16); }
@@ -171,11 +181,12 @@ int stage_ops_total(int Nc) { return MOps<DIM, N>::total((Nc + 15) / 16); }
 
 template <int DIM, int N, typename T>
 ShapeEntry shape_entry() {
-    ShapeEntry s{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N>, nullptr, nullptr, nullptr,
-                 nullptr};
+    ShapeEntry s{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N>, nullptr, nullptr, 0,
+                 nullptr, nullptr};
     if constexpr (batch_enabled<DIM, N, T>()) {
         s.batch_stage = &launch_stage_batch<DIM, N, T>;
         s.batch_lds = &stage_batch_lds<DIM, N, T>;
+        s.batch_waves_max = batch_max_waves<DIM, N, T>();
         s.batch_allow_lds = &batch_allow_lds<DIM, N, T>;
         s.batch_scratch = &batch_scratch<DIM, N, T>;
     }

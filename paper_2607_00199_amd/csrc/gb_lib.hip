@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -64,6 +65,7 @@ struct gb_ctx {
     hipStream_t stream = nullptr;
     int num_cu = 256;
     size_t max_lds = 65536;
+    std::string arch;               // gcnArchName, part of the tuning-cache key
     double *scratch = nullptr;      // this device's copy of the scratch array
 };
 
@@ -462,6 +464,8 @@ struct gb_batch {
         int64_t total = 0;          // element groups
         size_t lds = 0;
         int grid = 0;
+        int waves = gbd::kWaves;    // wavefronts per workgroup
+        bool interleave = false;    // groups dealt round robin instead of in ranges
         int vset = -1;              // its vertex subset (solo classes)
         const void *ops = nullptr;
         const int32_t *fmask = nullptr;
@@ -477,11 +481,21 @@ struct gb_batch {
     std::vector<VertexSet> vsets;
     int vsmall[2] = {-1, -1};
     int graph_steps = 0;            // steps held by the captured graph
-    std::map<std::array<int, 5>, int> tuned;   // (dim, N, precision, Nc, solo) -> grid
     hipGraphExec_t graph = nullptr;
     bool dirty = true;
+    // members stepped on their own run on these library-owned streams
+    // (default priority), up to `concurrency` at a time, so that one member's
+    // kernel tails overlap another's; each run forks them from the batch's
+    // stream and joins them back into it
+    int concurrency = 1;
+    std::vector<hipStream_t> aux;
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
     ~gb_batch() {
         if (graph) (void)hipGraphExecDestroy(graph);
+        for (auto e : join_ev) (void)hipEventDestroy(e);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        for (auto st : aux) (void)hipStreamDestroy(st);
     }
 };
 
@@ -490,6 +504,24 @@ namespace {
 // Element groups from which a member is stepped on its own (2048 groups of
 // 16 elements give one group to each wavefront of two workgroups per CU).
 constexpr int64_t kSoloGroups = 2048;
+
+// Launch tile of a batched class: workgroups, wavefronts per workgroup and
+// the group-to-workgroup mapping, chosen by timing (tune_class) and kept in a
+// process-wide cache keyed by device architecture, shape, precision,
+// cubature size, solo/shared and the power-of-two bucket of the element
+// groups; the cache can be saved to and loaded from a text file.
+struct Tile {
+    int grid = 0, waves = gbd::kWaves, interleave = 0;
+};
+std::mutex g_tile_mu;
+std::map<std::string, Tile> g_tiles;
+
+std::string tile_key(const gb_ctx *ctx, const gb_batch::Class &c) {
+    int bucket = 0;
+    while ((int64_t(2) << bucket) <= c.total) ++bucket;
+    return ctx->arch + " " + std::to_string(c.dim) + " " + std::to_string(c.N) + " " + std::to_string(c.prec) + " " +
+           std::to_string(c.Nc) + " " + std::to_string(c.solo ? 1 : 0) + " " + std::to_string(bucket);
+}
 
 size_t mesh_bytes(const gb_mesh *m) {
     return m->d_etov.bytes + m->d_X.bytes + m->d_x.bytes + m->d_vmapP.bytes + m->d_wv.bytes;
@@ -527,7 +559,8 @@ gb_status upload_class_table(gb_batch *b, gb_batch::Class &c) {
         const gb_solver *s0 = b->members[size_t(c.idx[0])].s;
         const std::string bad =
             gbh::check_batch_class(c.dim, s0->ref.Np, s0->NF, s0->ref.Nfaces * s0->ref.Nfp, sizeof(T), lay, gb, g,
-                                   gbd::kMaxBatch, c.shape.batch_lds(c.Nc, int(c.idx.size())), b->ctx->max_lds);
+                                   gbd::kMaxBatch, c.shape.batch_lds(c.Nc, int(c.idx.size()), gbd::kWaves),
+                                   b->ctx->max_lds);
         if (!bad.empty()) return fail(GB_ERR_STATE, "batch table check: " + bad);
     }
     c.total = g;
@@ -538,7 +571,7 @@ gb_status upload_class_table(gb_batch *b, gb_batch::Class &c) {
     return GB_OK;
 }
 
-gbd::BatchLaunch class_launch(const gb_batch::Class &c, int grid) {
+gbd::BatchLaunch class_launch(const gb_batch::Class &c, int grid, int waves, bool interleave) {
     gbd::BatchLaunch L;
     L.ent = c.ent.p;
     L.group_begin = c.gbeg.as<int32_t>();
@@ -546,7 +579,9 @@ gbd::BatchLaunch class_launch(const gb_batch::Class &c, int grid) {
     L.total = c.total;
     L.Nc = c.Nc;
     L.grid = grid;
-    L.lds = c.lds;
+    L.waves = waves;
+    L.interleave = interleave;
+    L.lds = c.shape.batch_lds(c.Nc, c.nreq, waves);
     L.ops = c.ops;
     L.fmask = c.fmask;
     return L;
@@ -573,8 +608,11 @@ hipError_t launch_vertex_batch(gb_batch *b, int set, bool finish, hipStream_t st
     return hipGetLastError();
 }
 
-// Launch grid of a class: the fastest of a few workgroup counts for stage 0,
-// timed on the members' current state (see gb.h: state is not changed).
+// Launch tile of a class: the fastest of the candidate tiles for stage 0
+// (workgroups per CU 1..16, four or eight wavefronts per workgroup where the
+// kernel allows eight, ranges or round-robin dealing of the groups), each
+// timed over three launches on the members' current state (see gb.h: the
+// state is not changed).
 gb_status tune_class(gb_batch *b, gb_batch::Class &c) {
     hipStream_t st = b->ctx->stream;
     GB_HIP(launch_vertex_batch(b, c.solo ? c.vset : b->vsmall[c.dim - 2], false, st));
@@ -582,31 +620,40 @@ gb_status tune_class(gb_batch *b, gb_batch::Class &c) {
     hipEvent_t e0, e1;
     GB_HIP(hipEventCreate(&e0));
     GB_HIP(hipEventCreate(&e1));
-    int best = b->ctx->num_cu * 8;
+    Tile best{b->ctx->num_cu * 2, gbd::kWaves, 0};
     float best_ms = 1e30f;
     gb_status r = GB_OK;
-    for (int mi = 0; mi < 5 && r == GB_OK; ++mi) {
-        const int grid = b->ctx->num_cu * mults[mi];
-        const gbd::BatchLaunch L = class_launch(c, grid);
-        hipError_t e = c.shape.batch_stage(L, 0, st);
-        if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = c.shape.batch_stage(L, 0, st);
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            r = fail(GB_ERR_DEVICE, std::string("batch tuning: ") + hipGetErrorString(e));
-            break;
-        }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = grid;
-        }
+    for (int waves = gbd::kWaves; waves <= c.shape.batch_waves_max && r == GB_OK; waves *= 2) {
+        if (c.shape.batch_lds(c.Nc, c.nreq, waves) > b->ctx->max_lds) continue;
+        for (int il = 0; il < 2 && r == GB_OK; ++il)
+            for (int mi = 0; mi < 5 && r == GB_OK; ++mi) {
+                const int grid = b->ctx->num_cu * mults[mi] * gbd::kWaves / waves;
+                if (grid < 1) continue;
+                const gbd::BatchLaunch L = class_launch(c, grid, waves, il != 0);
+                hipError_t e = c.shape.batch_stage(L, 0, st);
+                if (e == hipSuccess) e = hipEventRecord(e0, st);
+                for (int k = 0; k < 3 && e == hipSuccess; ++k) e = c.shape.batch_stage(L, 0, st);
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    r = fail(GB_ERR_DEVICE, std::string("batch tuning: ") + hipGetErrorString(e));
+                    break;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = Tile{grid, waves, il};
+                }
+            }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (r == GB_OK) c.grid = best;
+    if (r == GB_OK) {
+        c.grid = best.grid;
+        c.waves = best.waves;
+        c.interleave = best.interleave != 0;
+    }
     return r;
 }
 
@@ -650,14 +697,34 @@ gb_status batch_rebuild(gb_batch *b) {
         if (c.nreq > gbd::kMaxBatch) return fail(GB_ERR_UNSUPPORTED, "too many members in one class");
         const gb_status r = c.prec == GB_FP64 ? upload_class_table<double>(b, c) : upload_class_table<float>(b, c);
         if (r != GB_OK) return r;
-        c.lds = c.shape.batch_lds(c.Nc, c.nreq);
+        c.lds = c.shape.batch_lds(c.Nc, c.nreq, gbd::kWaves);
         if (c.lds > b->ctx->max_lds) return fail(GB_ERR_UNSUPPORTED, "batch class exceeds the LDS of one workgroup");
-        GB_HIP(c.shape.batch_allow_lds(c.lds));
+        // the dynamic-LDS limit of the kernels covers the largest workgroup tried
+        size_t lds_max = c.lds;
+        for (int w = 2 * gbd::kWaves; w <= c.shape.batch_waves_max; w *= 2) {
+            const size_t l = c.shape.batch_lds(c.Nc, c.nreq, w);
+            if (l <= b->ctx->max_lds) lds_max = std::max(lds_max, l);
+        }
+        GB_HIP(c.shape.batch_allow_lds(lds_max));
         const gb_solver *s0 = b->members[size_t(c.idx[0])].s;
         c.ops = s0->ops.p;
         c.fmask = s0->fmask.as<int32_t>();
-        auto it = b->tuned.find({c.dim, c.N, c.prec, c.Nc, int(c.solo)});
-        c.grid = it != b->tuned.end() ? it->second : b->ctx->num_cu * 2;
+        c.grid = b->ctx->num_cu * 2;
+        c.waves = gbd::kWaves;
+        c.interleave = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tile_mu);
+            auto it = g_tiles.find(tile_key(b->ctx, c));
+            // a cached tile this kernel cannot run (workgroup too large for its
+            // registers or for the LDS) is ignored
+            if (it != g_tiles.end() && it->second.waves <= c.shape.batch_waves_max &&
+                c.shape.batch_lds(c.Nc, c.nreq, it->second.waves) <= b->ctx->max_lds) {
+                c.grid = it->second.grid;
+                c.waves = it->second.waves;
+                c.interleave = it->second.interleave != 0;
+            }
+        }
+        c.lds = c.shape.batch_lds(c.Nc, c.nreq, c.waves);
     }
     {
         std::vector<gbd::MotionEntry> E;
@@ -717,33 +784,64 @@ gb_status batch_rebuild(gb_batch *b) {
     }
     if (b->autotune)
         for (auto &c : b->classes) {
-            const std::array<int, 5> key{c.dim, c.N, c.prec, c.Nc, int(c.solo)};
-            if (b->tuned.count(key)) continue;
+            const std::string key = tile_key(b->ctx, c);
+            {
+                std::lock_guard<std::mutex> lk(g_tile_mu);
+                if (g_tiles.count(key)) continue;
+            }
             const gb_status r = tune_class(b, c);
             if (r != GB_OK) return r;
-            b->tuned[key] = c.grid;
+            c.lds = c.shape.batch_lds(c.Nc, c.nreq, c.waves);
+            std::lock_guard<std::mutex> lk(g_tile_mu);
+            g_tiles[key] = Tile{c.grid, c.waves, c.interleave ? 1 : 0};
         }
     b->dirty = false;
     b->graph_steps = 0;
     return GB_OK;
 }
 
-// `steps` steps of every large member in turn (motion, four stages, end of
-// step), launched directly: a member whose state fits the last-level cache
-// keeps it there from step to step, and its kernels are long enough that
-// launch overhead does not matter.
-hipError_t batch_launch_solo(gb_batch *b, int steps, hipStream_t st) {
+// `steps` steps of every large member (motion, four stages, end of step),
+// launched directly: a member whose state fits the last-level cache keeps it
+// there from step to step, and its kernels are long enough that launch
+// overhead does not matter.  With concurrency > 1 the members are dealt to
+// the auxiliary streams round robin (a member always to the same stream, so
+// its steps stay ordered); otherwise they run in turn on `st`.
+hipError_t batch_launch_solo(gb_batch *b, int steps, hipStream_t st, int use) {
     hipError_t le = hipSuccess;
+    int n = 0;
     for (auto &c : b->classes) {
         if (!c.solo) continue;
+        hipStream_t cs = use > 1 ? b->aux[size_t(n++ % use)] : st;
         for (int k = 0; k < steps && le == hipSuccess; ++k) {
-            le = launch_vertex_batch(b, c.vset, false, st);
+            le = launch_vertex_batch(b, c.vset, false, cs);
             for (int kind = 0; kind < 4 && le == hipSuccess; ++kind)
-                le = c.shape.batch_stage(class_launch(c, c.grid), kind, st);
-            if (le == hipSuccess) le = launch_vertex_batch(b, c.vset, true, st);
+                le = c.shape.batch_stage(class_launch(c, c.grid, c.waves, c.interleave), kind, cs);
+            if (le == hipSuccess) le = launch_vertex_batch(b, c.vset, true, cs);
         }
     }
     return le;
+}
+
+int solo_count(const gb_batch *b) {
+    int n = 0;
+    for (const auto &c : b->classes) n += c.solo ? 1 : 0;
+    return n;
+}
+
+// Auxiliary streams for concurrency > 1 (created once, kept for the batch).
+gb_status ensure_aux(gb_batch *b) {
+    const int want = b->concurrency > 1 ? std::min(b->concurrency, solo_count(b)) : 0;
+    if (want <= 1) return GB_OK;
+    if (!b->fork_ev) GB_HIP(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+    while (int(b->aux.size()) < want) {
+        hipStream_t st;
+        GB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->aux.push_back(st);
+        hipEvent_t e;
+        GB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->join_ev.push_back(e);
+    }
+    return GB_OK;
 }
 
 bool has_small(const gb_batch *b) {
@@ -769,7 +867,8 @@ gb_status batch_capture(gb_batch *b, int steps) {
             for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, b->vsmall[di], false, cap);
             for (int kind = 0; kind < 4 && le == hipSuccess; ++kind)
                 for (auto &c : b->classes)
-                    if (le == hipSuccess && !c.solo) le = c.shape.batch_stage(class_launch(c, c.grid), kind, cap);
+                    if (le == hipSuccess && !c.solo)
+                        le = c.shape.batch_stage(class_launch(c, c.grid, c.waves, c.interleave), kind, cap);
             for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, b->vsmall[di], true, cap);
         }
         e = hipStreamEndCapture(cap, &g);
@@ -811,6 +910,9 @@ gb_status gb_ctx_create(int device, void *stream, gb_ctx **out) {
     GB_HIP(hipGetDeviceProperties(&prop, device));
     c->num_cu = prop.multiProcessorCount;
     c->max_lds = prop.sharedMemPerBlock;
+    c->arch = prop.gcnArchName;
+    for (char &ch : c->arch)
+        if (ch == ' ' || ch == ':') ch = '_';
     GB_HIP(scratch_addr(device, &c->scratch));
     *out = c.release();
     return GB_OK;
@@ -1787,10 +1889,30 @@ gb_status gb_batch_run(gb_batch *b, int64_t steps) {
         const gb_status r = batch_capture(b, k);
         if (r != GB_OK) return r;
     }
-    for (int64_t n = 0; n < steps / k; ++n) {
-        GB_HIP(batch_launch_solo(b, k, b->ctx->stream));
-        if (small) GB_HIP(hipGraphLaunch(b->graph, b->ctx->stream));
+    {
+        const gb_status r = ensure_aux(b);
+        if (r != GB_OK) return r;
     }
+    // as many auxiliary streams as there are solo members, at most the
+    // concurrency; they start after the work already on the batch's stream
+    const int use = b->concurrency > 1 ? std::min(int(b->aux.size()), solo_count(b)) : 0;
+    if (use > 1) {
+        GB_HIP(hipEventRecord(b->fork_ev, b->ctx->stream));
+        for (int i = 0; i < use; ++i) GB_HIP(hipStreamWaitEvent(b->aux[size_t(i)], b->fork_ev, 0));
+    }
+    hipError_t le = hipSuccess;
+    for (int64_t n = 0; n < steps / k && le == hipSuccess; ++n) {
+        le = batch_launch_solo(b, k, b->ctx->stream, use);
+        if (small && le == hipSuccess) le = hipGraphLaunch(b->graph, b->ctx->stream);
+    }
+    // the batch's stream waits for the auxiliary streams, so a synchronisation
+    // of it (gb_batch_poll, the next table rebuild) covers every member
+    for (int i = 0; use > 1 && i < use; ++i) {
+        const hipError_t e = hipEventRecord(b->join_ev[size_t(i)], b->aux[size_t(i)]);
+        if (e == hipSuccess) GB_HIP(hipStreamWaitEvent(b->ctx->stream, b->join_ev[size_t(i)], 0));
+        else if (le == hipSuccess) le = e;
+    }
+    GB_HIP(le);
     return GB_OK;
 }
 
@@ -1829,6 +1951,15 @@ gb_status gb_batch_info(const gb_batch *b, int *active, size_t *used_bytes, size
     return GB_OK;
 }
 
+gb_status gb_batch_set_concurrency(gb_batch *b, int streams) {
+    if (!b) return fail(GB_ERR_ARG, "NULL batch");
+    if (streams < 1 || streams > 8) return fail(GB_ERR_ARG, "streams must be 1..8");
+    GB_HIP(hipSetDevice(b->ctx->device));
+    GB_HIP(hipStreamSynchronize(b->ctx->stream));
+    b->concurrency = streams;
+    return GB_OK;
+}
+
 gb_status gb_batch_set_autotune(gb_batch *b, int enable) {
     if (!b) return fail(GB_ERR_ARG, "NULL batch");
     b->autotune = enable != 0;
@@ -1839,6 +1970,62 @@ gb_status gb_batch_class_count(const gb_batch *b, int *n) {
     if (!b || !n) return fail(GB_ERR_ARG, "NULL argument");
     *n = int(b->classes.size());
     return GB_OK;
+}
+
+gb_status gb_batch_class_tile(const gb_batch *b, int i, int64_t *tile) {
+    if (!b || !tile) return fail(GB_ERR_ARG, "NULL argument");
+    if (i < 0 || i >= int(b->classes.size())) return fail(GB_ERR_ARG, "class index out of range");
+    const gb_batch::Class &c = b->classes[size_t(i)];
+    tile[0] = c.grid;
+    tile[1] = c.waves;
+    tile[2] = c.interleave ? 1 : 0;
+    return GB_OK;
+}
+
+gb_status gb_tune_cache_save(const char *path) {
+    if (!path) return fail(GB_ERR_ARG, "NULL path");
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(GB_ERR_ARG, std::string("cannot write ") + path);
+    std::fprintf(f, "# gb launch tiles: arch dim N precision Nc solo group-bucket : grid waves interleave\n");
+    for (const auto &kv : g_tiles)
+        std::fprintf(f, "%s : %d %d %d\n", kv.first.c_str(), kv.second.grid, kv.second.waves, kv.second.interleave);
+    std::fclose(f);
+    return GB_OK;
+}
+
+gb_status gb_tune_cache_load(const char *path, int *entries) {
+    if (!path) return fail(GB_ERR_ARG, "NULL path");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(GB_ERR_ARG, std::string("cannot read ") + path);
+    char line[512];
+    int n = 0;
+    std::map<std::string, Tile> add;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#') continue;
+        const char *colon = std::strchr(line, ':');
+        if (!colon) continue;
+        std::string key(line, size_t(colon - line));
+        while (!key.empty() && key.back() == ' ') key.pop_back();
+        Tile t;
+        if (std::sscanf(colon + 1, "%d %d %d", &t.grid, &t.waves, &t.interleave) != 3 || t.grid < 1 ||
+            (t.waves != gbd::kWaves && t.waves != 2 * gbd::kWaves)) {
+            std::fclose(f);
+            return fail(GB_ERR_ARG, "malformed tuning-cache line: " + std::string(line));
+        }
+        add[key] = t;
+        ++n;
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    for (const auto &kv : add) g_tiles[kv.first] = kv.second;
+    if (entries) *entries = n;
+    return GB_OK;
+}
+
+void gb_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    g_tiles.clear();
 }
 
 gb_status gb_batch_class_info(const gb_batch *b, int i, int64_t *info) {

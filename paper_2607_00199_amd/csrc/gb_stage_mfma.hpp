@@ -147,9 +147,9 @@ __host__ __device__ constexpr int stage_lds_arrays() {
 }
 
 template <int DIM, int N, typename T>
-__host__ __device__ inline size_t mfma_lds_bytes(int nct) {
+__host__ __device__ inline size_t mfma_lds_bytes(int nct, int waves = kWaves) {
     using S = Shape<DIM, N>;
-    const size_t state = size_t(stage_lds_arrays<DIM, N, T>()) * kWaves * S::NF * S::NP * 16 * sizeof(T);
+    const size_t state = size_t(stage_lds_arrays<DIM, N, T>()) * waves * S::NF * S::NP * 16 * sizeof(T);
     return mfma_lds_state_offset<DIM, N, T>(nct) + state;
 }
 
@@ -283,15 +283,27 @@ struct BatchArgs {
     const int32_t *group_begin;      // [nreq]: first group of each entry, ascending
     int nreq;
     int total;                       // groups over all entries
-    int chunk;                       // groups per workgroup
+    int chunk;                       // groups per workgroup (contiguous ranges)
+    int stride;                      // > 0: workgroups take every stride-th block of waves groups instead
     int Nc;
     const T *ops;
     const int32_t *fmask;
 };
 
+// Dynamic LDS of the batched kernel for a workgroup of `waves` wavefronts:
+// the single-mesh layout sized for that many wavefronts, then the group
+// offsets of the nreq entries.
 template <int DIM, int N, typename T>
-inline size_t batch_lds_bytes(int nct, int nreq) {
-    return (mfma_lds_bytes<DIM, N, T>(nct) + 15) / 16 * 16 + size_t(nreq) * sizeof(int32_t);
+__host__ __device__ inline size_t batch_lds_bytes(int nct, int nreq, int waves) {
+    return (mfma_lds_bytes<DIM, N, T>(nct, waves) + 15) / 16 * 16 + size_t(nreq) * sizeof(int32_t);
+}
+
+// Workgroup sizes the batched kernel can run with: four wavefronts, or
+// eight where the kernel targets two wavefronts per SIMD (its registers then
+// allow eight of them on the four SIMDs of a CU).
+template <int DIM, int N, typename T>
+__host__ __device__ constexpr int batch_max_waves() {
+    return stage_waves_per_eu<DIM, N>(sizeof(T)) >= 2 ? 2 * kWaves : kWaves;
 }
 
 // Batched stage kernel (request-table form, see gb.h): the groups of every
@@ -307,7 +319,8 @@ __host__ __device__ constexpr bool batch_enabled() {
 }
 
 template <int DIM, int N, typename T, int STAGE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<DIM, N>(sizeof(T)))))
+__global__ void __launch_bounds__((64 * batch_max_waves<DIM, N, T>()))
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<DIM, N>(sizeof(T)))))
 stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
     using S = Shape<DIM, N>;
     using MS = MShape<DIM, N>;
@@ -324,7 +337,8 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
     int32_t *s_slot = reinterpret_cast<int32_t *>(smem + (size_t(nops) * sizeof(T) + 15) / 16 * 16);
     for (int p = threadIdx.x; p < nops; p += blockDim.x) s_ops[p] = b.ops[p];
     for (int p = threadIdx.x; p < 2 * O::slots(); p += blockDim.x) s_slot[p] = b.fmask[p];
-    int32_t *s_gb = reinterpret_cast<int32_t *>(smem + (mfma_lds_bytes<DIM, N, T>(nct) + 15) / 16 * 16);
+    int32_t *s_gb =
+        reinterpret_cast<int32_t *>(smem + (mfma_lds_bytes<DIM, N, T>(nct, int(blockDim.x >> 6)) + 15) / 16 * 16);
     for (int p = threadIdx.x; p < b.nreq; p += blockDim.x) s_gb[p] = b.group_begin[p];
     __syncthreads();
 
@@ -340,9 +354,18 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
 
     int logical = blockIdx.x;
     if ((gridDim.x & 7) == 0) logical = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-    const int g_begin = logical * b.chunk;
-    int g_end = g_begin + b.chunk;
-    if (g_end > b.total) g_end = b.total;
+    // a contiguous range of groups per workgroup, or (tuning option) blocks of
+    // nwave consecutive groups dealt to the workgroups round robin
+    int g_begin, g_end, g_step;
+    if (b.stride > 0) {
+        g_begin = logical * nwave;
+        g_end = b.total;
+        g_step = b.stride * nwave;
+    } else {
+        g_begin = logical * b.chunk;
+        g_end = g_begin + b.chunk < b.total ? g_begin + b.chunk : b.total;
+        g_step = nwave;
+    }
 
     // As in stage_mfma_kernel, triangle kernels load the vertex ids and the
     // first two trace-map entries of a wave's next group (found in the table,
@@ -365,7 +388,7 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
         for (int v = 0; v < NVERT; ++v) pf_vid[v] = et[(en < En.K ? en : 0) * NVERT + v];
     };
 
-    for (int gi = g_begin + wave; gi < g_end; gi += nwave) {
+    for (int gi = g_begin + wave; gi < g_end; gi += g_step) {
         const int gt = __builtin_amdgcn_readfirstlane(gi);
         const int r = __builtin_amdgcn_readfirstlane(table_search(s_gb, b.nreq, gt));
         const BatchEntry<T> &E = ent[r];
@@ -396,7 +419,7 @@ stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
         const int g = gt - s_gb[r];
         if (kPF && !pf_ok) prefetch(gt);
         // table index of this wave's next group (the body prefetches it)
-        const int pf_next = gi + nwave < g_end ? gt + nwave : -1;
+        const int pf_next = gi + g_step < g_end ? gt + g_step : -1;
         pf_ok = pf_next >= 0;
 #include "gb_stage_body.inc"
     }

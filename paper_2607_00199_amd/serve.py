@@ -22,6 +22,7 @@ request runs in libgb.so.
 from __future__ import annotations
 
 import math
+import os
 import time
 from collections import deque
 from dataclasses import dataclass
@@ -109,15 +110,22 @@ class Server:
     batch's queued steps.  Both streams are non-blocking streams of the
     library's own HIP runtime."""
 
-    def __init__(self, budget_bytes: int, device: int = 0, steps_per_launch: int = 5, autotune: bool = True):
+    def __init__(self, budget_bytes: int, device: int = 0, steps_per_launch: int = 5, autotune: bool = True,
+                 tune_cache: str | None = None, concurrency: int = 1):
         self.streams = [L.gb_stream_create(device), L.gb_stream_create(device)]
         self.run_ctx = L.gb_ctx_create(device, self.streams[0])
         self.setup_ctx = L.gb_ctx_create(device, self.streams[1])
         self.batch = L.gb_batch_create(self.run_ctx, budget_bytes)
         L.gb_batch_set_autotune(self.batch, autotune)
+        if concurrency > 1:
+            L.gb_batch_set_concurrency(self.batch, concurrency)
         self.budget = int(budget_bytes)
         self.steps_per_launch = int(steps_per_launch)
         self.classes = []
+        # launch tiles from earlier runs (gb_tune_cache_*), saved again at close
+        self.tune_cache = tune_cache
+        if tune_cache and os.path.exists(tune_cache):
+            L.gb_tune_cache_load(tune_cache)
 
     # -------------------------------------------------------------- requests
     def _prepare(self, r: Request):
@@ -231,6 +239,8 @@ class Server:
 
     def close(self):
         if self.batch:
+            if self.tune_cache:
+                L.gb_tune_cache_save(self.tune_cache)
             L.gb_batch_destroy(self.batch)
             self.batch = None
             L.gb_ctx_destroy(self.setup_ctx)

@@ -345,3 +345,87 @@ def test_served_fp64_requests_match_oracle():
         scale = np.abs(o.q).max(axis=(0, 2))
         assert r.steps_done == r.nsteps
         assert (np.abs(r.state - o.q).max(axis=(0, 2)) <= 1e-12 * np.maximum(scale, 1e-3)).all(), r.index
+
+
+def test_tile_cache_and_results_independent_of_the_tile(tmp_path):
+    """The autotuner's tile (workgroups, wavefronts per workgroup, group
+    dealing) is kept in a cache that can be saved and loaded; a batch run
+    with a tile forced from a loaded cache (eight wavefronts, round-robin
+    dealing) gives every member the same bits as the tuned run."""
+    L.gb_tune_cache_clear()
+    ctx = L.gb_ctx_create(0, 0)
+    mix = [(make_case("C1", n=8, N=4), L.GB_FP32, 5), (make_case("C1", n=6, N=4), L.GB_FP32, 4),
+           (make_case("C1", n=8, N=3), L.GB_FP64, 3)]
+
+    def run(autotune):
+        reqs = [_Req(ctx, c, p) for c, p, _ in mix]
+        b = L.gb_batch_create(ctx, BIG)
+        L.gb_batch_set_autotune(b, autotune)
+        for r, (c, p, n) in zip(reqs, mix):
+            L.gb_batch_add(b, r.solver, c.dt, n)
+        L.gb_batch_run(b, 5)
+        tiles = [(L.gb_batch_class_info(b, i)["precision"], L.gb_batch_class_tile(b, i))
+                 for i in range(L.gb_batch_class_count(b))]
+        assert len(L.gb_batch_poll(b)) == 3
+        out = [r.state()[0] for r in reqs]
+        L.gb_batch_destroy(b)
+        for r in reqs:
+            r.close()
+        return out, tiles
+
+    q1, tiles1 = run(True)
+    path = str(tmp_path / "tiles.txt")
+    L.gb_tune_cache_save(path)
+    lines = [ln for ln in open(path) if not ln.startswith("#")]
+    assert len(lines) == 2                                   # one FP32 and one FP64 class
+    forced = []
+    for ln in lines:
+        key, val = ln.split(":")
+        grid = int(val.split()[0])
+        forced.append(f"{key.strip()} : {grid} 8 1\n")       # eight wavefronts, round robin
+    with open(path, "w") as f:
+        f.writelines(forced)
+    L.gb_tune_cache_clear()
+    assert L.gb_tune_cache_load(path) == 2
+    q2, tiles2 = run(False)
+    for prec, t in tiles2:
+        if prec == L.GB_FP32:
+            assert t["waves"] == 8 and t["interleave"] == 1
+        else:                                               # FP64 kernels run four wavefronts only
+            assert t["waves"] == 4
+    for a, b in zip(q1, q2):
+        assert np.array_equal(a, b)
+    with open(path, "w") as f:
+        f.write("gfx950 2 4 1 49 0 3 : twelve\n")
+    with pytest.raises(L.GbError) as ei:
+        L.gb_tune_cache_load(path)
+    assert ei.value.status == L.GB_ERR_ARG
+    L.gb_tune_cache_clear()
+    L.gb_ctx_destroy(ctx)
+
+
+def test_large_members_on_concurrent_streams_match_alone():
+    """Three members large enough to be stepped on their own, run on three
+    streams at once, and a small one in the shared launch: every result equals
+    the member as the only member of a batch, bit for bit."""
+    ctx = L.gb_ctx_create(0, 0)
+    mix = [(make_case("C1", n=128, N=2), L.GB_FP32, 3), (make_case("C1", n=128, N=3, seed=4), L.GB_FP32, 4),
+           (make_case("C2", n=128, N=2), L.GB_FP32, 2), (make_case("C1", n=8, N=2), L.GB_FP32, 4)]
+    ref = [_alone_batch(ctx, c, p, n) for c, p, n in mix]
+    reqs = [_Req(ctx, c, p) for c, p, _ in mix]
+    b = L.gb_batch_create(ctx, BIG)
+    L.gb_batch_set_concurrency(b, 3)
+    for r, (c, p, n) in zip(reqs, mix):
+        L.gb_batch_add(b, r.solver, c.dt, n)
+    L.gb_batch_run(b, 2)
+    L.gb_batch_run(b, 2)
+    info = [L.gb_batch_class_info(b, i) for i in range(L.gb_batch_class_count(b))]
+    assert sum(d["solo"] for d in info) == 3
+    assert len(L.gb_batch_poll(b)) == 4
+    for i, r in enumerate(reqs):
+        q, t, step = r.state()
+        assert step == mix[i][2] and np.array_equal(q, ref[i][0]), i
+    L.gb_batch_destroy(b)
+    for r in reqs:
+        r.close()
+    L.gb_ctx_destroy(ctx)
