@@ -222,7 +222,7 @@ def run_served(args, requests=None, steps=None) -> dict:
     print(f"served: {len(reqs)} request meshes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     budget = int(args.budget_gib * (1 << 30)) if args.budget_gib > 0 else (1 << 50)
     srv = S.Server(budget, steps_per_launch=args.steps_per_launch, concurrency=args.concurrency,
-                   autotune=not args.no_autotune)
+                   autotune=not args.no_autotune, max_steps_per_launch=args.max_steps_per_launch)
     stats = srv.serve(reqs)
     srv.close()
     print(f"served: {stats['completed']} done in {stats['makespan_s']:.1f} s", file=sys.stderr, flush=True)
@@ -277,7 +277,9 @@ def main():
     ap.add_argument("--steps-per-launch", type=int, default=5)
     ap.add_argument("--serial-steps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true", help="batched classes use the default launch tile")
-    ap.add_argument("--concurrency", type=int, default=1,
+    ap.add_argument("--max-steps-per-launch", type=int, default=64,
+                    help="with no request waiting, run up to the next completion, at most this many steps")
+    ap.add_argument("--concurrency", type=int, default=3,
                     help="streams on which large batch members run at once")
     ap.add_argument("--no-served", action="store_true",
                     help="skip the bounded served run appended to the default line")

@@ -45,12 +45,34 @@ struct BatchLaunch {
     const int32_t *fmask = nullptr;
 };
 
+// Builds a graph of kernel nodes, each depending on the previous one (the
+// batched form's replayed steps), without stream capture: the graph can be
+// built while other threads make HIP calls.
+struct GraphAppender {
+    hipGraph_t g = nullptr;
+    hipGraphNode_t last = nullptr;
+    hipError_t add(const void *func, dim3 grid, dim3 block, size_t lds, void **params) {
+        hipKernelNodeParams np{};
+        np.func = const_cast<void *>(func);
+        np.gridDim = grid;
+        np.blockDim = block;
+        np.sharedMemBytes = unsigned(lds);
+        np.kernelParams = params;
+        np.extra = nullptr;
+        hipGraphNode_t node;
+        const hipError_t e = hipGraphAddKernelNode(&node, g, last ? &last : nullptr, last ? 1 : 0, &np);
+        if (e == hipSuccess) last = node;
+        return e;
+    }
+};
+
 struct ShapeEntry {
     hipError_t (*stage)(const LaunchArgs &, int kind, hipStream_t);
     size_t (*lds)(int Nc);
     int (*ops_total)(int Nc);
     // batched form; null for the shapes it is not built for
     hipError_t (*batch_stage)(const BatchLaunch &, int kind, hipStream_t);
+    hipError_t (*batch_node)(const BatchLaunch &, int kind, GraphAppender &);
     size_t (*batch_lds)(int Nc, int nreq, int waves);
     int batch_waves_max;
     // raises the dynamic-LDS limit of the batched kernels (outside capture)
@@ -104,9 +126,10 @@ hipError_t launch_stage(const LaunchArgs &L, int kind, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Kernel arguments and grid of a batched stage launch.
 template <int DIM, int N, typename T>
-hipError_t launch_stage_batch(const BatchLaunch &L, int kind, hipStream_t st) {
-    BatchArgs<T> b{};
+int batch_launch_config(const BatchLaunch &L, BatchArgs<T> &b) {
+    b = BatchArgs<T>{};
     b.ent = static_cast<const BatchEntry<T> *>(L.ent);
     b.group_begin = L.group_begin;
     b.nreq = L.nreq;
@@ -127,12 +150,31 @@ hipError_t launch_stage_batch(const BatchLaunch &L, int kind, hipStream_t st) {
         b.chunk = 1;
         b.stride = grid;
     }
+    return grid;
+}
+
+template <int DIM, int N, typename T>
+hipError_t launch_stage_batch(const BatchLaunch &L, int kind, hipStream_t st) {
+    BatchArgs<T> b;
+    const int grid = batch_launch_config<DIM, N, T>(L, b);
     using K0 = decltype(&stage_batch_kernel<DIM, N, T, 0>);
     const K0 fns[5] = {&stage_batch_kernel<DIM, N, T, 0>, &stage_batch_kernel<DIM, N, T, 1>,
                        &stage_batch_kernel<DIM, N, T, 2>, &stage_batch_kernel<DIM, N, T, 3>,
                        &stage_batch_kernel<DIM, N, T, 4>};
-    hipLaunchKernelGGL(fns[kind < 4 ? kind : 4], dim3(grid), dim3(64 * waves), L.lds, st, b, b.ent);
+    hipLaunchKernelGGL(fns[kind < 4 ? kind : 4], dim3(grid), dim3(64 * L.waves), L.lds, st, b, b.ent);
     return hipGetLastError();
+}
+
+template <int DIM, int N, typename T>
+hipError_t node_stage_batch(const BatchLaunch &L, int kind, GraphAppender &ga) {
+    BatchArgs<T> b;
+    const int grid = batch_launch_config<DIM, N, T>(L, b);
+    const BatchEntry<T> *ent = b.ent;
+    const void *fns[5] = {(const void *)&stage_batch_kernel<DIM, N, T, 0>, (const void *)&stage_batch_kernel<DIM, N, T, 1>,
+                          (const void *)&stage_batch_kernel<DIM, N, T, 2>, (const void *)&stage_batch_kernel<DIM, N, T, 3>,
+                          (const void *)&stage_batch_kernel<DIM, N, T, 4>};
+    void *params[2] = {&b, &ent};
+    return ga.add(fns[kind < 4 ? kind : 4], dim3(grid), dim3(64 * L.waves), L.lds, params);
 }
 
 template <int DIM, int N, typename T>
@@ -181,10 +223,11 @@ int stage_ops_total(int Nc) { return MOps<DIM, N>::total((Nc + 15) / 16); }
 
 template <int DIM, int N, typename T>
 ShapeEntry shape_entry() {
-    ShapeEntry s{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N>, nullptr, nullptr, 0,
+    ShapeEntry s{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N>, nullptr, nullptr, nullptr, 0,
                  nullptr, nullptr};
     if constexpr (batch_enabled<DIM, N, T>()) {
         s.batch_stage = &launch_stage_batch<DIM, N, T>;
+        s.batch_node = &node_stage_batch<DIM, N, T>;
         s.batch_lds = &stage_batch_lds<DIM, N, T>;
         s.batch_waves_max = batch_max_waves<DIM, N, T>();
         s.batch_allow_lds = &batch_allow_lds<DIM, N, T>;

@@ -608,6 +608,22 @@ hipError_t launch_vertex_batch(gb_batch *b, int set, bool finish, hipStream_t st
     return hipGetLastError();
 }
 
+// The vertex kernel of a set as a node of a graph under construction.
+hipError_t node_vertex_batch(gb_batch *b, int set, bool finish, gbd::GraphAppender &ga) {
+    if (set < 0) return hipSuccess;
+    const gb_batch::VertexSet &vs = b->vsets[size_t(set)];
+    if (vs.n == 0) return hipSuccess;
+    const int blk = 256;
+    const unsigned nb = unsigned((vs.vtot + blk - 1) / blk);
+    const gbd::MotionEntry *E = b->mot.as<gbd::MotionEntry>() + vs.first;
+    int n = vs.n;
+    int64_t vtot = vs.vtot;
+    void *params[3] = {&E, &n, &vtot};
+    const void *fn = vs.dim == 2 ? (finish ? (const void *)&gbd::finish_batch_kernel<2> : (const void *)&gbd::motion_batch_kernel<2>)
+                                 : (finish ? (const void *)&gbd::finish_batch_kernel<3> : (const void *)&gbd::motion_batch_kernel<3>);
+    return ga.add(fn, dim3(nb), dim3(blk), 0, params);
+}
+
 // Launch tile of a class: the fastest of the candidate tiles for stage 0
 // (workgroups per CU 1..16, four or eight wavefronts per workgroup where the
 // kernel allows eight, ranges or round-robin dealing of the groups), each
@@ -851,34 +867,30 @@ bool has_small(const gb_batch *b) {
 }
 
 // The graph of `steps` steps of the small members (one launch per class and
-// stage), captured on a private stream.
+// stage), built node by node (no stream capture, so other threads may make
+// HIP calls meanwhile, e.g. a served loop's setup worker).
 gb_status batch_capture(gb_batch *b, int steps) {
     if (b->graph) {
         GB_HIP(hipGraphExecDestroy(b->graph));
         b->graph = nullptr;
     }
-    hipStream_t cap;
-    GB_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipError_t le = hipSuccess;
-        for (int k = 0; k < steps && le == hipSuccess; ++k) {
-            for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, b->vsmall[di], false, cap);
-            for (int kind = 0; kind < 4 && le == hipSuccess; ++kind)
-                for (auto &c : b->classes)
-                    if (le == hipSuccess && !c.solo)
-                        le = c.shape.batch_stage(class_launch(c, c.grid, c.waves, c.interleave), kind, cap);
-            for (int di = 0; di < 2 && le == hipSuccess; ++di) le = launch_vertex_batch(b, b->vsmall[di], true, cap);
-        }
-        e = hipStreamEndCapture(cap, &g);
-        if (e == hipSuccess && le != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            e = le;
-        }
+    GB_HIP(hipGraphCreate(&g, 0));
+    gbd::GraphAppender ga;
+    ga.g = g;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < steps && e == hipSuccess; ++k) {
+        for (int di = 0; di < 2 && e == hipSuccess; ++di) e = node_vertex_batch(b, b->vsmall[di], false, ga);
+        for (int kind = 0; kind < 4 && e == hipSuccess; ++kind)
+            for (auto &c : b->classes)
+                if (e == hipSuccess && !c.solo)
+                    e = c.shape.batch_node(class_launch(c, c.grid, c.waves, c.interleave), kind, ga);
+        for (int di = 0; di < 2 && e == hipSuccess; ++di) e = node_vertex_batch(b, b->vsmall[di], true, ga);
     }
-    (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) return fail(GB_ERR_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(GB_ERR_DEVICE, std::string("batch graph build: ") + hipGetErrorString(e));
+    }
     e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(GB_ERR_DEVICE, std::string("batch graph instantiate: ") + hipGetErrorString(e));

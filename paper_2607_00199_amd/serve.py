@@ -1,17 +1,19 @@
 """Served form: a request loop over the batched C ABI.
 
 Requests (each a mesh, order, precision, parameters and a step count) arrive
-over time.  The loop runs the batch a few steps at a time (gb_batch_run,
-asynchronous) and, while those steps run on the GPU,
+over time.  The loop keeps the batch stepping (gb_batch_run, asynchronous,
+a few steps at a time while requests wait for admission, up to the next
+completion otherwise) while a worker thread does the host-side setup on a
+separate stream:
 
-  * builds the meshes of newly arrived requests;
-  * prepares the next admissions in arrival order: a request is taken while
+  * the mesh of every arrived request (connectivity, trace map, upload);
+  * for the requests admitted in arrival order -- a request is taken while
     its device footprint (gb_solver_footprint + gb_mesh_footprint) fits the
-    free part of the budget (one that does not fit waits, and so does every
-    request behind it); its solver is created and its initial state uploaded
-    on a separate stream;
+    free part of the budget, and one that does not fit waits, and so does
+    every request behind it -- the solver and its initial state;
+  * the final state of the requests that completed;
 
-then, at the step boundary, retires the requests that reached their step
+at each step boundary the loop retires the requests that reached their step
 count (gb_batch_poll; latency = completion - arrival) and adds the prepared
 ones to the batch (gb_batch_add).
 
@@ -25,6 +27,7 @@ import math
 import os
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -111,7 +114,7 @@ class Server:
     library's own HIP runtime."""
 
     def __init__(self, budget_bytes: int, device: int = 0, steps_per_launch: int = 5, autotune: bool = True,
-                 tune_cache: str | None = None, concurrency: int = 1):
+                 tune_cache: str | None = None, concurrency: int = 1, max_steps_per_launch: int = 0):
         self.streams = [L.gb_stream_create(device), L.gb_stream_create(device)]
         self.run_ctx = L.gb_ctx_create(device, self.streams[0])
         self.setup_ctx = L.gb_ctx_create(device, self.streams[1])
@@ -121,6 +124,9 @@ class Server:
             L.gb_batch_set_concurrency(self.batch, concurrency)
         self.budget = int(budget_bytes)
         self.steps_per_launch = int(steps_per_launch)
+        # when no request is waiting, the batch runs up to the next completion
+        # (at most this many steps, in multiples of 8) between step boundaries
+        self.max_steps_per_launch = int(max_steps_per_launch)
         self.classes = []
         # launch tiles from earlier runs (gb_tune_cache_*), saved again at close
         self.tune_cache = tune_cache
@@ -168,61 +174,99 @@ class Server:
     # -------------------------------------------------------------- loop
     def serve(self, requests, clock=time.perf_counter, sleep=time.sleep) -> dict:
         pend = deque(sorted(requests, key=lambda q: q.arrival))
-        queue: deque = deque()          # arrived, not yet admitted
-        staged: list = []               # admitted, solver ready, not yet in the batch
+        queue: deque = deque()          # arrived, in arrival order (setup of the mesh submitted)
+        staged: list = []               # admitted, solver setup submitted, not yet in the batch
         active: dict = {}
+        remaining: dict = {}            # ticket -> steps still to run
         finished = []
+        prep, stg, fin = {}, {}, []     # futures of the host-side setup work
+        # Host-side setup (mesh connectivity, solver creation, initial state,
+        # final-state download) runs on one worker thread on the setup
+        # context's stream, so the stepping loop keeps the GPU fed meanwhile.
+        pool = ThreadPoolExecutor(max_workers=1)
         t0 = clock()
 
         def intake():
             now = clock() - t0
             while pend and pend[0].arrival <= now:
-                queue.append(pend.popleft())
-            for r in queue:
-                if r._mesh is None:
-                    self._prepare(r)
+                r = pend.popleft()
+                queue.append(r)
+                prep[id(r)] = pool.submit(self._prepare, r)
             _, used, _ = L.gb_batch_info(self.batch)
             free = self.budget - used - sum(r.bytes for r in staged)
-            for _ in range(admit_fifo([r.bytes for r in queue], free)):
-                r = queue.popleft()
-                self._stage(r)
+            # arrival order, no overtaking: stop at the first request whose
+            # mesh is not ready yet or whose footprint does not fit
+            while queue and prep[id(queue[0])].done():
+                r = queue[0]
+                prep[id(r)].result()
+                if r.bytes > free:
+                    break
+                queue.popleft()
+                free -= r.bytes
                 r.t_admit = clock() - t0
+                stg[id(r)] = pool.submit(self._stage, r)
                 staged.append(r)
 
-        while pend or queue or staged or active:
-            if not active:
-                intake()
-            for r in staged:
+        def join_staged(block: bool):
+            while staged and (block or stg[id(staged[0])].done()):
+                r = staged.pop(0)
+                stg.pop(id(r)).result()
+                block = False
                 try:
-                    active[L.gb_batch_add(self.batch, r._solver, r.case.dt, r.nsteps)] = r
+                    tk = L.gb_batch_add(self.batch, r._solver, r.case.dt, r.nsteps)
+                    active[tk] = r
+                    remaining[tk] = r.nsteps
                 except L.GbError as ex:
                     # a request the batch cannot take (a shape the batched
                     # kernel is not built for, a full table) fails on its own
                     r.error = str(ex)
                     r.t_done = clock() - t0
-                    self._release(r)
+                    fin.append(pool.submit(self._release, r))
                     finished.append(r)
-            staged.clear()
-            if not active:
-                if queue:
-                    # nothing running and the head still does not fit: it never will
-                    r = queue.popleft()
-                    r.rejected = True
-                    self._release(r)
+
+        try:
+            while pend or queue or staged or active:
+                intake()
+                join_staged(block=False)
+                if not active:
+                    if staged:
+                        join_staged(block=True)
+                    elif queue:
+                        r = queue[0]
+                        prep[id(r)].result()
+                        _, used, _ = L.gb_batch_info(self.batch)
+                        if r.bytes > self.budget - used:
+                            # nothing running and the head does not fit: it never will
+                            queue.popleft()
+                            r.rejected = True
+                            fin.append(pool.submit(self._release, r))
+                            finished.append(r)
+                    elif pend:
+                        sleep(max(0.0, pend[0].arrival - (clock() - t0)))
+                    continue
+                n = self.steps_per_launch
+                if self.max_steps_per_launch > n and not pend and not queue and not staged:
+                    # nobody waits for admission: run to the next completion
+                    n = max(n, min(min(remaining.values()), self.max_steps_per_launch))
+                    if n >= 8:
+                        n -= n % 8
+                L.gb_batch_run(self.batch, n)
+                for tk in remaining:
+                    remaining[tk] = max(0, remaining[tk] - n)
+                if not self.classes:
+                    self.classes = [L.gb_batch_class_info(self.batch, i)
+                                    for i in range(L.gb_batch_class_count(self.batch))]
+                intake()                     # overlaps the steps just enqueued
+                for ticket in L.gb_batch_poll(self.batch, len(active)):
+                    remaining.pop(ticket, None)
+                    r = active.pop(ticket)
+                    r.t_done = clock() - t0
+                    fin.append(pool.submit(self._finish, r))
                     finished.append(r)
-                elif pend:
-                    sleep(max(0.0, pend[0].arrival - (clock() - t0)))
-                continue
-            L.gb_batch_run(self.batch, self.steps_per_launch)
-            if not self.classes:
-                self.classes = [L.gb_batch_class_info(self.batch, i)
-                                for i in range(L.gb_batch_class_count(self.batch))]
-            intake()                     # overlaps the steps just enqueued
-            for ticket in L.gb_batch_poll(self.batch, len(active)):
-                r = active.pop(ticket)
-                r.t_done = clock() - t0
-                self._finish(r)
-                finished.append(r)
+        finally:
+            pool.shutdown(wait=True)
+        for f in fin:
+            f.result()
         done = [r for r in finished if not r.rejected and r.error is None]
         lat = [r.t_done - r.arrival for r in done]
         work = sum(4.0 * r.dof * r.nsteps for r in done)

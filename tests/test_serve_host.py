@@ -211,3 +211,30 @@ def test_served_loop_request_the_batch_refuses_fails_alone(monkeypatch):
     assert stats["failed"] == 1 and reqs[1].error and "not built" in reqs[1].error
     assert stats["completed"] == 2 and all(reqs[i].steps_done == 4 for i in (0, 2))
     assert fake.live == 0
+
+
+def test_served_loop_runs_to_the_next_completion_when_nobody_waits(monkeypatch):
+    """With max_steps_per_launch set, the loop runs long stretches once every
+    request has been admitted; every request still stops at its own step
+    count and the budget is respected."""
+    from paper_2607_00199_amd import serve as S
+    from workloads import make_case
+    sim = [0.0]
+    cases = [make_case("C1", n=n, N=2) for n in (4, 6, 8, 5)]
+    fake = _FakeLib(sim)
+    runs = []
+    orig = fake.gb_batch_run
+
+    def run(b, steps):
+        runs.append(steps)
+        orig(b, steps)
+
+    fake.gb_batch_run = run
+    monkeypatch.setattr(S, "L", fake)
+    srv = S.Server(1 << 40, steps_per_launch=2, max_steps_per_launch=40)
+    reqs = [S.Request(index=i, arrival=0.0, case=c, nsteps=n) for i, (c, n) in enumerate(zip(cases, (50, 7, 23, 90)))]
+    stats = srv.serve(reqs, clock=lambda: sim[0], sleep=lambda dt: sim.__setitem__(0, sim[0] + dt))
+    assert stats["completed"] == 4
+    assert all(r.steps_done == r.nsteps for r in reqs)
+    assert max(runs) > 2 and max(runs) <= 40
+    assert fake.live == 0
