@@ -155,6 +155,35 @@ def run_other(name: str, steps: int, warmup: int) -> dict:
             "frac": round(b / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def energy_series(name: str, steps: int, every: int) -> dict:
+    """Kinetic energy E_K and its rate eps = -dE_K/dt (Section 7.2) every
+    `every` steps of an FP32 run of a workload, with the rate also estimated
+    by centred differences of the E_K series as a consistency check."""
+    from paper_2607_00199_amd import _lib as L
+    from paper_2607_00199_amd.session import Session
+    from workloads import make_case
+
+    case = make_case(name)
+    s = Session(case, precision=L.GB_FP32, device=0, stream=0)
+    s.set_state(s.initial_state())
+    t, ek, eps = [], [], []
+    done = 0
+    while True:
+        e, r, _ = s.energy()
+        t.append(done * case.dt)
+        ek.append(e)
+        eps.append(r)
+        if done >= steps:
+            break
+        n = min(every, steps - done)
+        s.step(case.dt, n)
+        done += n
+    s.close()
+    fd = [None] + [-(ek[i + 1] - ek[i - 1]) / (t[i + 1] - t[i - 1]) for i in range(1, len(t) - 1)] + [None]
+    return {"workload": name, "K": s.K, "N": case.N, "dim": case.dim, "dt": case.dt, "precision": "f32",
+            "t": t, "E_K": ek, "eps": eps, "eps_centred_difference": fd}
+
+
 def host_cores() -> int:
     """Host cores this process may use (its CPU affinity), at most 16 (the
     host share of one GPU on a shared node)."""
@@ -281,6 +310,9 @@ def main():
                     help="with no request waiting, run up to the next completion, at most this many steps")
     ap.add_argument("--concurrency", type=int, default=3,
                     help="streams on which large batch members run at once")
+    ap.add_argument("--energy-series", metavar="WORKLOAD", default=None,
+                    help="print the E_K / eps series of an FP32 run of WORKLOAD (e.g. C3) and exit")
+    ap.add_argument("--series-every", type=int, default=25)
     ap.add_argument("--no-served", action="store_true",
                     help="skip the bounded served run appended to the default line")
     ap.add_argument("--served-requests-default", type=int, default=16,
@@ -295,6 +327,10 @@ def main():
 
     if args.served:
         main_served(args)
+        return
+    if args.energy_series:
+        steps = args.steps if "--steps" in sys.argv else 500
+        print(json.dumps({"energy_series": energy_series(args.energy_series, steps, args.series_every)}))
         return
 
     import numpy as np
