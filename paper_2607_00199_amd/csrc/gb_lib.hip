@@ -334,17 +334,22 @@ std::vector<T> pack_ops(const gbh::RefElement &R, std::vector<int32_t> &slot_tab
         for (int lane = 0; lane < 64; ++lane) o.push_back(T(val(lane & 15, lane >> 4)));
     };
     auto at = [](const gbh::Mat &M, int i, int j) { return (i < M.rows && j < M.cols) ? M(i, j) : 0.0; };
+    // a thin last node tile (FP32, at most four real rows) is contracted by
+    // 4x4x1 blocks: lane (q, c) holds row 16 rt + c % 4 instead of 16 rt + c
+    const bool thin = f32 && Np - 16 * (NRT - 1) <= 4;
+    auto row = [&](int rt, int c) { return 16 * rt + ((thin && rt == NRT - 1) ? (c & 3) : c); };
     for (int a = 0; a < dim; ++a)
         for (int rt = 0; rt < NRT; ++rt)
             for (int st = 0; st < NJS; ++st)
-                frag([&](int c, int q) { return at(R.D[a], 16 * rt + c, 4 * st + q); });
+                frag([&](int c, int q) { return at(R.D[a], row(rt, c), 4 * st + q); });
     for (int rt = 0; rt < NRT; ++rt)
-        for (int st = 0; st < NMS; ++st) frag([&](int c, int q) { return at(R.LIFT, 16 * rt + c, 4 * st + q); });
+        for (int st = 0; st < NMS; ++st) frag([&](int c, int q) { return at(R.LIFT, row(rt, c), 4 * st + q); });
     for (int t = 0; t < nct; ++t)
         for (int st = 0; st < NJS; ++st) frag([&](int c, int q) { return at(R.Icub, 16 * t + c, 4 * st + q); });
     for (int rt = 0; rt < NRT; ++rt)
         for (int t = 0; t < nct; ++t)
-            for (int r = 0; r < 4; ++r) frag([&](int c, int q) { return at(R.Pcub, 16 * rt + c, 16 * t + crow(q, r)); });
+            for (int r = 0; r < 4; ++r)
+                frag([&](int c, int q) { return at(R.Pcub, row(rt, c), 16 * t + crow(q, r)); });
     for (int i = 0; i < Np; ++i)
         for (int v = 0; v < nvert; ++v) o.push_back(T(R.bary(i, v)));
     slot_table.assign(size_t(4 * NMS) * 2, -1);

@@ -57,6 +57,25 @@ __host__ __device__ constexpr int crow(int q, int r) {
     return sizeof(T) == 4 ? 4 * q + r : q + 4 * r;
 }
 
+// Sixteen independent 4x4x1 products (v_mfma_f32_4x4x1f32, a quarter of the
+// cycles of the 16x16x4 form).  Measured lane layout on gfx950: lane l holds
+// A(block l/4, row l%4), B(block l/4, column l%4) and, in slot r, the result
+// (block l/4, row r, column l%4).  With block = 4 (l/16) + (l%16)/4 this is
+// a 4-row tile over the 16 element columns whose contraction is split four
+// ways by lane/16: the B operand is exactly the 16x16x4 form's, and the four
+// partial sums of a column are added across lanes l, l+16, l+32, l+48.
+__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+// The last 16-row node tile holds at most four real rows (tetrahedra of
+// order 1 and 3, triangles of order 1) and the state is FP32: that tile is
+// contracted with mfma4 instead of mfma16.
+template <int DIM, int N, typename T>
+__host__ __device__ constexpr bool thin_last_tile() {
+    return sizeof(T) == 4 && Shape<DIM, N>::NP - 16 * ((Shape<DIM, N>::NP + 15) / 16 - 1) <= 4;
+}
+
 // Entry (row, col) of the flux pattern M_d (A_d = -c M_d).
 template <int DIM>
 __host__ __device__ constexpr double mcoef(int d, int row, int col) {

@@ -29,14 +29,17 @@ BIG = 1 << 40
 
 
 def _mix():
-    """(case, precision, nsteps): triangles of orders 2-4 in FP32 and FP64, a
-    walled O-grid with far field and sponge, and tetrahedra."""
+    """(case, precision, nsteps): triangles of orders 1-4 in FP32 and FP64, a
+    walled O-grid with far field and sponge, and tetrahedra of orders 1 and 2
+    (the order-1 shapes contract their single node tile by 4x4x1 blocks)."""
     return [
         (make_case("C4", n_r=8, n_theta=16, N=2), L.GB_FP32, 7),
         (make_case("C1", n=8, N=4), L.GB_FP32, 12),
         (make_case("C3", n=3, N=2), L.GB_FP32, 5),
         (make_case("C1", n=8, N=3), L.GB_FP64, 9),
         (make_case("C1", n=6, N=4), L.GB_FP32, 4),
+        (make_case("C3", n=3, N=1), L.GB_FP32, 6),
+        (make_case("C1", n=6, N=1), L.GB_FP32, 5),
     ]
 
 
@@ -93,13 +96,13 @@ def test_batch_alone_vs_mix_bitwise():
     b = L.gb_batch_create(ctx, BIG)
     reqs = [_Req(ctx, c, p) for c, p, _ in mix]
     tickets = {}
-    # the first three join at once, the other two after two launches
+    # the first three join at once, the others after two launches
     for i in range(3):
         tickets[L.gb_batch_add(b, reqs[i].solver, mix[i][0].dt, mix[i][2])] = i
     L.gb_batch_run(b, 2)
     assert L.gb_batch_poll(b) == []
     L.gb_batch_run(b, 1)
-    for i in (3, 4):
+    for i in range(3, len(mix)):
         tickets[L.gb_batch_add(b, reqs[i].solver, mix[i][0].dt, mix[i][2])] = i
     done = []
     for _ in range(20):
