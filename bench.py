@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp"],
-    "sha256": "cf830e310397540f5004e857974e6381a74668d8d261d6e449410726abb02958",
+    "sha256": "17180e9f42343b04cdb4112fe2b81111b843c6aaff9b2608ecdfbd73f113bdd9",
     "K": 131072,
-    "bytes_per_launch": 214757 * 1024,
+    "bytes_per_launch": 213184 * 1024,
 }
 
 
