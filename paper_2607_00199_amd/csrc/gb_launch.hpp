@@ -17,6 +17,7 @@ struct LaunchArgs {
     int64_t nv = 0;
     int Nc = 0;
     int grid = 1;              // workgroups for a full chip (CUs x 8)
+    bool interleave = false;   // groups dealt to workgroups round robin instead of in ranges
     size_t lds = 0;            // dynamic LDS bytes per workgroup
     const int32_t *etov = nullptr;
     const double *vstage = nullptr;   // [5][nv][dim] stage vertex positions
@@ -95,6 +96,7 @@ hipError_t launch_stage(const LaunchArgs &L, int kind, hipStream_t st) {
     grid = (a.nbatch + a.chunk - 1) / a.chunk;
     // the XCD-major remap needs a multiple of 8; surplus workgroups find no group
     if (grid >= 8 && grid % 8) grid = (grid + 7) / 8 * 8;
+    a.stride = L.interleave ? grid : 0;
     a.etov = L.etov;
     {
         const int64_t stride = L.nv * DIM;

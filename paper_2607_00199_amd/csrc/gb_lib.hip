@@ -128,6 +128,7 @@ struct gb_solver {
     bool has_state = false;
     bool in_batch = false;          // a batch member: stepped and read only through its batch
     int grid = 1;
+    bool interleave = false;        // stage launches deal groups round robin instead of in ranges
     size_t lds = 0;
     // timing: an event pair around every stage launch, resolved on query
     bool timing = false;
@@ -173,6 +174,11 @@ void fill_coef(gbd::StageCoef<T> &c, const gbh::SarkCoef &h, double dt) {
     c.b1 = T(dt * h.b[1]);
     c.b2 = T(dt * h.b[2]);
     c.b3 = T(dt * h.b[3]);
+    // weights of q_n1 - E1 q_n = a10 F0, which replaces F0 (a10 = phi1(c1
+    // gamma) / 2 > 0 before the dt factor, which cancels in the ratios)
+    c.r20 = T(h.a20 / h.a10);
+    c.rb0 = T(h.b[0] / h.a10);
+    c.r30 = T(h.a30 / h.a10);
 }
 
 // coefficients turning the five eigenvalue weights into powers of M_n:
@@ -278,6 +284,7 @@ hipError_t Launcher::stage(gb_solver *s, int kind, double dt, hipStream_t st) co
     a.nv = m->nv;
     a.Nc = s->ref.Nc;
     a.grid = s->grid;
+    a.interleave = s->interleave;
     a.lds = s->lds;
     a.etov = m->d_etov.as<int32_t>();
     a.vstage = s->vstage.as<double>();
@@ -1247,6 +1254,11 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     // element groups (the operator fragments are staged in LDS once per
     // workgroup); measured faster than one workgroup per group
     s->grid = m->ctx->num_cu * 2;
+    // Tetrahedra deal their groups round robin: the groups in flight then form
+    // one contiguous window, so face neighbours a few cube rows away are
+    // gathered while still in L2 (measured 3.8 % faster on the 3D TGV); on
+    // the triangle workloads both dealings measured the same.
+    s->interleave = m->dim == 3;
     GB_HIP(hipSetDevice(m->ctx->device));
     const size_t n = size_t((m->K + 15) / 16 * 16) * s->NF * Np;   // padded to whole groups of 16
     if (s->Q.alloc(n * s->elem_bytes) != hipSuccess || s->A.alloc(n * s->elem_bytes) != hipSuccess ||

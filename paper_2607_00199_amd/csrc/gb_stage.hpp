@@ -32,6 +32,13 @@ struct StageCoef {
     T E1, E2, E3, E4;
     T a10, a20, a21, a30, a32;
     T b0, b1, b2, b3;
+    // Stage 0 stores q_n1 = E1 q_n + a10 F0 in place of F0, so the later
+    // combinations take a10 F0 = q_n1 - E1 q_n with the weights divided by
+    // a10: q_n2 = E2 q_n + r20 (q_n1 - E1 q_n) + a21 F1, likewise G (rb0) and
+    // q_n3 (r30).  q_n keeps its exact weight E (1 for the density class, so
+    // no bias accumulates in FP32), and the difference is of the size of the
+    // increment.
+    T r20, rb0, r30;
 };
 
 // Per-solver constants that change only with dt; kept in device memory and
@@ -55,6 +62,8 @@ struct KArgs {
     int nbatch;          // number of 16-element groups, ceil(K / 16)
     int Nc;              // cubature points
     int chunk;           // batches per workgroup
+    int stride;          // 0: each workgroup a contiguous range of chunk groups;
+                         // else blocks of (wavefronts) groups dealt round robin
     const int32_t *etov;
     const double *xs;    // vertex positions of this stage [nv][DIM]
     const double *ws;    // grid velocity at the vertices for this stage [nv][DIM]

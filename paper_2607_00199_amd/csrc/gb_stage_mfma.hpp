@@ -157,8 +157,8 @@ __host__ __device__ constexpr bool stage_in_lds() {
 }
 
 // Blocks of the group's state staged per wavefront: two where they fit (the
-// stage input and a second array the stage combination needs: q_n and F0 in
-// stage 1, G in stage 3), one otherwise (triangles of order 5 in FP64: about
+// stage input and a second array the stage combination needs: q_n in stage
+// 1, G in stage 3), one otherwise (triangles of order 5 in FP64: about
 // 47 KB of fragments plus 16 KB per block and wavefront).
 template <int DIM, int N, typename T>
 __host__ __device__ constexpr int stage_lds_arrays() {
@@ -194,11 +194,12 @@ __device__ __forceinline__ KConstRef<T> kconst_ref(const KConst<T> *p) {
 // evaluated.
 template <int NCONS, int STAGE, typename T>
 __device__ __forceinline__ T stage_in_at(const T *Q, const T *A, const T *B, KConstRef<T> kc, int k, int64_t off) {
+    (void)kc;
+    (void)k;
     if constexpr (STAGE == kStage0 || STAGE == kRhsOnly) {
         return Q[off];
     } else if constexpr (STAGE == kStage1) {
-        const auto &c = kc.cf[k < NCONS ? 0 : 1];
-        return c.E1 * Q[off] + c.a10 * A[off];
+        return A[off];   // q_n1, stored by stage 0
     } else if constexpr (STAGE == kStage2) {
         (void)Q;
         return B[off];
@@ -248,9 +249,18 @@ stage_mfma_kernel(KArgs<T> a) {
 
     int logical = blockIdx.x;
     if ((gridDim.x & 7) == 0) logical = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-    const int g_begin = logical * a.chunk;
-    int g_end = g_begin + a.chunk;
-    if (g_end > a.nbatch) g_end = a.nbatch;
+    // a contiguous range of groups per workgroup, or blocks of nwave
+    // consecutive groups dealt to the workgroups round robin
+    int g_begin, g_end, g_step;
+    if (a.stride > 0) {
+        g_begin = logical * nwave;
+        g_end = a.nbatch;
+        g_step = a.stride * nwave;
+    } else {
+        g_begin = logical * a.chunk;
+        g_end = g_begin + a.chunk < a.nbatch ? g_begin + a.chunk : a.nbatch;
+        g_step = nwave;
+    }
 
     // Triangle kernels load the vertex ids and the first two trace-map
     // entries of a wave's next group while the current group computes, so a
@@ -268,9 +278,9 @@ stage_mfma_kernel(KArgs<T> a) {
     };
     if (kPF && g_begin + wave < g_end) prefetch(g_begin + wave);
 
-    for (int gi = g_begin + wave; gi < g_end; gi += nwave) {
+    for (int gi = g_begin + wave; gi < g_end; gi += g_step) {
         const int g = __builtin_amdgcn_readfirstlane(gi);
-        const int pf_next = gi + nwave < g_end ? g + nwave : -1;
+        const int pf_next = gi + g_step < g_end ? g + g_step : -1;
 #include "gb_stage_body.inc"
     }
 }
