@@ -351,12 +351,21 @@ std::vector<T> pack_ops(const gbh::RefElement &R, std::vector<int32_t> &slot_tab
                 frag([&](int c, int q) { return at(R.D[a], row(rt, c), 4 * st + q); });
     for (int rt = 0; rt < NRT; ++rt)
         for (int st = 0; st < NMS; ++st) frag([&](int c, int q) { return at(R.LIFT, row(rt, c), 4 * st + q); });
+    // a thin last cubature tile (at most four real points, FP32): 4x4x1
+    // interpolation rows 16 t + c % 4, projection over points 16 t + q in slot 0
+    const bool thin_c = gbd::thin_cub_tile(Nc, f32);
     for (int t = 0; t < nct; ++t)
-        for (int st = 0; st < NJS; ++st) frag([&](int c, int q) { return at(R.Icub, 16 * t + c, 4 * st + q); });
+        for (int st = 0; st < NJS; ++st)
+            frag([&](int c, int q) {
+                return at(R.Icub, 16 * t + ((thin_c && t == nct - 1) ? (c & 3) : c), 4 * st + q);
+            });
     for (int rt = 0; rt < NRT; ++rt)
         for (int t = 0; t < nct; ++t)
             for (int r = 0; r < 4; ++r)
-                frag([&](int c, int q) { return at(R.Pcub, row(rt, c), 16 * t + crow(q, r)); });
+                frag([&](int c, int q) {
+                    if (thin_c && t == nct - 1) return r == 0 ? at(R.Pcub, row(rt, c), 16 * t + q) : 0.0;
+                    return at(R.Pcub, row(rt, c), 16 * t + crow(q, r));
+                });
     for (int i = 0; i < Np; ++i)
         for (int v = 0; v < nvert; ++v) o.push_back(T(R.bary(i, v)));
     slot_table.assign(size_t(4 * NMS) * 2, -1);

@@ -76,6 +76,15 @@ __host__ __device__ constexpr bool thin_last_tile() {
     return sizeof(T) == 4 && Shape<DIM, N>::NP - 16 * ((Shape<DIM, N>::NP + 15) / 16 - 1) <= 4;
 }
 
+// The last 16-point cubature tile holds at most four real points (FP32; the
+// 49-point rule of the order-4 triangle has one): it is interpolated by
+// 4x4x1 blocks, lane (q, c) then takes point 16 t + q of element c, and the
+// projection over those four points is one 16x16x4 product (fragment slot
+// r = 0 holds P(row, 16 t + q); slots 1..3 are unused).
+__host__ __device__ constexpr bool thin_cub_tile(int Nc, bool f32) {
+    return f32 && Nc - 16 * ((Nc + 15) / 16 - 1) <= 4;
+}
+
 // Entry (row, col) of the flux pattern M_d (A_d = -c M_d).
 template <int DIM>
 __host__ __device__ constexpr double mcoef(int d, int row, int col) {
