@@ -602,7 +602,7 @@ Connectivity build_connectivity(const RefElement &R, int64_t nv, const double *v
             const int nfv = dim;
             FaceKey key;
             double cen[3] = {0, 0, 0};
-            std::vector<std::array<int64_t, 3>> pts(nfv);
+            std::array<std::array<int64_t, 3>, 3> pts{};
             for (int a = 0; a < nfv; ++a) {
                 const int lv = dim == 2 ? fv2[f][a] : fv3[f][a];
                 const int32_t gv = etov[e * nvert + lv];
@@ -615,7 +615,7 @@ Connectivity build_connectivity(const RefElement &R, int64_t nv, const double *v
                     pts[a][d] = quant(wrap(vx[int64_t(gv) * dim + d], d));
                 }
             }
-            std::sort(pts.begin(), pts.end());
+            std::sort(pts.begin(), pts.begin() + nfv);
             for (int d = 0; d < dim; ++d) key.k[d] = quant(wrap(cen[d], d));
             for (int a = 0; a < nfv; ++a)
                 for (int d = 0; d < 3; ++d) key.k[3 + 3 * a + d] = pts[a][d];
@@ -642,6 +642,7 @@ Connectivity build_connectivity(const RefElement &R, int64_t nv, const double *v
         }
     };
     C.vmapP.assign(size_t(K) * Nf * Nfp, 0);
+    std::vector<double> xnb(size_t(Nfp) * 3);
     for (int64_t e = 0; e < K; ++e)
         for (int f = 0; f < Nf; ++f) {
             const int64_t e2 = C.etoe[e * Nf + f];
@@ -657,13 +658,15 @@ Connectivity build_connectivity(const RefElement &R, int64_t nv, const double *v
                 continue;
             }
             const int f2 = etof[e * Nf + f];
+            // the neighbour face's node coordinates, once per face
+            for (int l = 0; l < Nfp; ++l) node_x(e2, R.fmask[f2 * Nfp + l], &xnb[size_t(l) * 3]);
             for (int m = 0; m < Nfp; ++m) {
-                double xa[3], xb[3];
+                double xa[3];
                 node_x(e, R.fmask[f * Nfp + m], xa);
                 double best = 1e300;
                 int bj = -1;
                 for (int l = 0; l < Nfp; ++l) {
-                    node_x(e2, R.fmask[f2 * Nfp + l], xb);
+                    const double *xb = &xnb[size_t(l) * 3];
                     double d2 = 0.0;
                     for (int d = 0; d < dim; ++d) {
                         double dd = xa[d] - xb[d];

@@ -114,7 +114,8 @@ class Server:
     library's own HIP runtime."""
 
     def __init__(self, budget_bytes: int, device: int = 0, steps_per_launch: int = 5, autotune: bool = True,
-                 tune_cache: str | None = None, concurrency: int = 1, max_steps_per_launch: int = 0):
+                 tune_cache: str | None = None, concurrency: int = 1, max_steps_per_launch: int = 0,
+                 setup_workers: int = 4):
         self.streams = [L.gb_stream_create(device), L.gb_stream_create(device)]
         self.run_ctx = L.gb_ctx_create(device, self.streams[0])
         self.setup_ctx = L.gb_ctx_create(device, self.streams[1])
@@ -128,6 +129,8 @@ class Server:
         # (at most this many steps, in multiples of 8) between step boundaries
         self.max_steps_per_launch = int(max_steps_per_launch)
         self.classes = []
+        # host threads building request meshes (connectivity) at once
+        self.setup_workers = max(1, int(setup_workers))
         # launch tiles from earlier runs (gb_tune_cache_*), saved again at close
         self.tune_cache = tune_cache
         if tune_cache and os.path.exists(tune_cache):
@@ -180,10 +183,13 @@ class Server:
         remaining: dict = {}            # ticket -> steps still to run
         finished = []
         prep, stg, fin = {}, {}, []     # futures of the host-side setup work
-        # Host-side setup (mesh connectivity, solver creation, initial state,
-        # final-state download) runs on one worker thread on the setup
-        # context's stream, so the stepping loop keeps the GPU fed meanwhile.
+        # Host-side setup runs on worker threads on the setup context's
+        # stream, so the stepping loop keeps the GPU fed meanwhile: mesh
+        # builds (host connectivity, the longest part) on several threads,
+        # solver creation, initial state and final-state download in order on
+        # one.
         pool = ThreadPoolExecutor(max_workers=1)
+        mesh_pool = ThreadPoolExecutor(max_workers=self.setup_workers)
         t0 = clock()
 
         def intake():
@@ -191,7 +197,7 @@ class Server:
             while pend and pend[0].arrival <= now:
                 r = pend.popleft()
                 queue.append(r)
-                prep[id(r)] = pool.submit(self._prepare, r)
+                prep[id(r)] = mesh_pool.submit(self._prepare, r)
             _, used, _ = L.gb_batch_info(self.batch)
             free = self.budget - used - sum(r.bytes for r in staged)
             # arrival order, no overtaking: stop at the first request whose
@@ -264,6 +270,7 @@ class Server:
                     fin.append(pool.submit(self._finish, r))
                     finished.append(r)
         finally:
+            mesh_pool.shutdown(wait=True)
             pool.shutdown(wait=True)
         for f in fin:
             f.result()
