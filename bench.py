@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp"],
-    "sha256": "17180e9f42343b04cdb4112fe2b81111b843c6aaff9b2608ecdfbd73f113bdd9",
+    "sha256": "c02274f9a2f46dc63a8c9734462a3bd776c63a1ec24a7899246462182f0d84de",
     "K": 131072,
-    "bytes_per_launch": 213184 * 1024,
+    "bytes_per_launch": 205474 * 1024,
 }
 
 

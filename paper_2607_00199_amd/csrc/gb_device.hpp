@@ -168,6 +168,20 @@ __device__ __forceinline__ double rsq_nr(double x) {
     y = fma(y, fma(-h * y, y, 0.5), y);
     return fma(y, fma(-h * y, y, 0.5), y);
 }
+// The same, refined only as far as a result that is cast to T needs: one
+// Newton step (relative error about 2^-44) when T is FP32, two for FP64.
+template <typename T>
+__device__ __forceinline__ double rcp_for(double x) {
+    if constexpr (sizeof(T) == 8) return rcp_nr(x);
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+template <typename T>
+__device__ __forceinline__ double rsq_for(double x) {
+    if constexpr (sizeof(T) == 8) return rsq_nr(x);
+    const double y = __builtin_amdgcn_rsq(x);
+    return fma(y, fma(-0.5 * x * y, y, 0.5), y);
+}
 
 // Nonlinear relaxation source Ntilde (Section 4) for the stress fields,
 // given density and momentum at a point: m_a m_b / (tau rho) off the
