@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp"],
-    "sha256": "c02274f9a2f46dc63a8c9734462a3bd776c63a1ec24a7899246462182f0d84de",
+    "sha256": "eb1eef62f88d8a10933a4d979d572cdc1b17b0b1d85a678bb8d9849ce7834221",
     "K": 131072,
-    "bytes_per_launch": 205474 * 1024,
+    "bytes_per_launch": 205461 * 1024,
 }
 
 

@@ -220,12 +220,12 @@ size_t stage_batch_lds(int Nc, int nreq, int waves) { return batch_lds_bytes<DIM
 template <int DIM, int N, typename T>
 size_t stage_lds(int Nc) { return mfma_lds_bytes<DIM, N, T>((Nc + 15) / 16); }
 
-template <int DIM, int N>
-int stage_ops_total(int Nc) { return MOps<DIM, N>::total((Nc + 15) / 16); }
+template <int DIM, int N, typename T>
+int stage_ops_total(int Nc) { return MOps<DIM, N, T>::total((Nc + 15) / 16); }
 
 template <int DIM, int N, typename T>
 ShapeEntry shape_entry() {
-    ShapeEntry s{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N>, nullptr, nullptr, nullptr, 0,
+    ShapeEntry s{&launch_stage<DIM, N, T>, &stage_lds<DIM, N, T>, &stage_ops_total<DIM, N, T>, nullptr, nullptr, nullptr, 0,
                  nullptr, nullptr};
     if constexpr (batch_enabled<DIM, N, T>()) {
         s.batch_stage = &launch_stage_batch<DIM, N, T>;

@@ -333,18 +333,19 @@ __global__ void from_state_kernel(const T *in, double *out, int64_t n, int NP, i
 template <typename T>
 std::vector<T> pack_ops(const gbh::RefElement &R, std::vector<int32_t> &slot_table) {
     const int dim = R.dim, Np = R.Np, NFT = R.Nfaces * R.Nfp, Nc = R.Nc, nvert = dim + 1;
-    const int NJS = (Np + 3) / 4, NRT = (Np + 15) / 16, NMS = (NFT + 3) / 4, nct = (Nc + 15) / 16;
     const bool f32 = sizeof(T) == 4;
+    const int NJS = (Np + 3) / 4, NRT = gbd::tiles_all(Np, f32), NMS = (NFT + 3) / 4, nct = (Nc + 15) / 16;
     auto crow = [&](int q, int r) { return f32 ? 4 * q + r : q + 4 * r; };
     std::vector<T> o;
     auto frag = [&](auto val) {
         for (int lane = 0; lane < 64; ++lane) o.push_back(T(val(lane & 15, lane >> 4)));
     };
     auto at = [](const gbh::Mat &M, int i, int j) { return (i < M.rows && j < M.cols) ? M(i, j) : 0.0; };
-    // a thin last node tile (FP32, at most four real rows) is contracted by
-    // 4x4x1 blocks: lane (q, c) holds row 16 rt + c % 4 instead of 16 rt + c
-    const bool thin = f32 && Np - 16 * (NRT - 1) <= 4;
-    auto row = [&](int rt, int c) { return 16 * rt + ((thin && rt == NRT - 1) ? (c & 3) : c); };
+    // thin node tiles (FP32, the last at most eight rows in tiles of four)
+    // are contracted by 4x4x1 blocks: lane (q, c) holds row
+    // tile_row0(rt) + c % 4 instead of 16 rt + c
+    const int nfull = gbd::tiles_full(Np, f32);
+    auto row = [&](int rt, int c) { return rt < nfull ? 16 * rt + c : gbd::tile_row0(rt, nfull) + (c & 3); };
     for (int a = 0; a < dim; ++a)
         for (int rt = 0; rt < NRT; ++rt)
             for (int st = 0; st < NJS; ++st)

@@ -68,13 +68,30 @@ __device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
-// The last 16-row node tile holds at most four real rows (tetrahedra of
-// order 1 and 3, triangles of order 1) and the state is FP32: that tile is
-// contracted with mfma4 instead of mfma16.
-template <int DIM, int N, typename T>
-__host__ __device__ constexpr bool thin_last_tile() {
-    return sizeof(T) == 4 && Shape<DIM, N>::NP - 16 * ((Shape<DIM, N>::NP + 15) / 16 - 1) <= 4;
+// Row tiles of the node contractions.  A 16-row tile runs on 16x16x4
+// products.  In FP32, a last 16-row tile with at most kThinRows real rows
+// (tetrahedra of order 1 and 3, triangles of order 1) is replaced by 4-row
+// thin tiles on mfma4: tile rt >= nfull holds rows 16 nfull + 4 (rt - nfull)
+// + r in every lane, as four partial sums over the contraction index split
+// by lane/16.  Two thin tiles for a last tile of 5 to 8 rows (triangles of
+// order 2 and 5) measured slower than one 16-row tile (order 5: 313 ->
+// 329 us per stage on the airfoil O-grid): their cross-lane reductions and
+// accumulators cost more than the products saved.
+constexpr int kThinRows = 4;
+__host__ __device__ constexpr int tiles_full(int np, bool f32) {
+    return (f32 && np - 16 * ((np + 15) / 16 - 1) <= kThinRows) ? (np + 15) / 16 - 1 : (np + 15) / 16;
 }
+__host__ __device__ constexpr int tiles_all(int np, bool f32) {
+    return tiles_full(np, f32) + (tiles_full(np, f32) == (np + 15) / 16 ? 0 : (np - 16 * tiles_full(np, f32) + 3) / 4);
+}
+__host__ __device__ constexpr int tile_row0(int rt, int nfull) { return rt < nfull ? 16 * rt : 16 * nfull + 4 * (rt - nfull); }
+
+template <int DIM, int N, typename T>
+struct Tiles {
+    static constexpr int NFULL = tiles_full(Shape<DIM, N>::NP, sizeof(T) == 4);
+    static constexpr int NRT = tiles_all(Shape<DIM, N>::NP, sizeof(T) == 4);
+    static constexpr bool THIN = NRT > NFULL;
+};
 
 // The last 16-point cubature tile holds at most four real points (FP32; the
 // 49-point rule of the order-4 triangle has one): it is interpolated by
@@ -124,24 +141,27 @@ struct MShape {
 };
 
 // Packed operator fragments (type T, 64 lane-ordered values per fragment):
-//   FD [DIM][NRT][NJS]   lane (q, c): D_a(16 rt + c, 4 s + q)
-//   FL [NRT][NMS]        LIFT(16 rt + c, 4 s + q)
+//   FD [DIM][NRT][NJS]   lane (q, c): D_a(row(rt, c), 4 s + q)
+//   FL [NRT][NMS]        LIFT(row(rt, c), 4 s + q)
 //   FI [NCT][NJS]        Icub(16 t + c, 4 s + q)
-//   FP [NRT][NCT][4]     Pcub(16 rt + c, 16 t + crow(q, r))
+//   FP [NRT][NCT][4]     Pcub(row(rt, c), 16 t + crow(q, r))
 //   BARY [NP][NVERT]
-// then an int table SLOT [4 NMS][2]: (volume node, face) of face slot m, or -1.
-template <int DIM, int N>
+// with row(rt, c) = 16 rt + c on a 16-row tile and tile_row0(rt) + c % 4 on a
+// thin one (NRT counts both kinds), then an int table SLOT [4 NMS][2]:
+// (volume node, face) of face slot m, or -1.
+template <int DIM, int N, typename T>
 struct MOps {
     using M = MShape<DIM, N>;
     using S = Shape<DIM, N>;
-    __host__ __device__ static constexpr int fd(int a, int rt, int s) { return ((a * M::NRT + rt) * M::NJS + s) * 64; }
-    __host__ __device__ static constexpr int fl(int rt, int s) { return (DIM * M::NRT * M::NJS + rt * M::NMS + s) * 64; }
-    __host__ __device__ static constexpr int fi_base() { return (DIM * M::NRT * M::NJS + M::NRT * M::NMS) * 64; }
+    static constexpr int NRT = Tiles<DIM, N, T>::NRT;
+    __host__ __device__ static constexpr int fd(int a, int rt, int s) { return ((a * NRT + rt) * M::NJS + s) * 64; }
+    __host__ __device__ static constexpr int fl(int rt, int s) { return (DIM * NRT * M::NJS + rt * M::NMS + s) * 64; }
+    __host__ __device__ static constexpr int fi_base() { return (DIM * NRT * M::NJS + NRT * M::NMS) * 64; }
     __host__ __device__ static int fi(int nct, int t, int s) { (void)nct; return fi_base() + (t * M::NJS + s) * 64; }
     __host__ __device__ static int fp(int nct, int rt, int t, int r) {
         return fi_base() + nct * M::NJS * 64 + ((rt * nct + t) * 4 + r) * 64;
     }
-    __host__ __device__ static int bary(int nct) { return fi_base() + nct * M::NJS * 64 + M::NRT * nct * 4 * 64; }
+    __host__ __device__ static int bary(int nct) { return fi_base() + nct * M::NJS * 64 + NRT * nct * 4 * 64; }
     __host__ __device__ static int total(int nct) { return bary(nct) + S::NP * S::NVERT; }
     __host__ __device__ static constexpr int slots() { return 4 * M::NMS; }
 };
@@ -152,9 +172,9 @@ constexpr int kWaves = 4;
 
 template <int DIM, int N, typename T>
 __host__ __device__ inline size_t mfma_lds_state_offset(int nct) {
-    size_t b = size_t(MOps<DIM, N>::total(nct)) * sizeof(T);
+    size_t b = size_t(MOps<DIM, N, T>::total(nct)) * sizeof(T);
     b = (b + 15) / 16 * 16;
-    b += size_t(MOps<DIM, N>::slots()) * 2 * sizeof(int32_t);
+    b += size_t(MOps<DIM, N, T>::slots()) * 2 * sizeof(int32_t);
     return (b + 15) / 16 * 16;
 }
 
@@ -230,10 +250,10 @@ __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_e
 stage_mfma_kernel(KArgs<T> a) {
     using S = Shape<DIM, N>;
     using MS = MShape<DIM, N>;
-    using O = MOps<DIM, N>;
+    using O = MOps<DIM, N, T>;
     using V = typename Vec4<T>::type;
     constexpr int NP = S::NP, NF = S::NF, NFT = S::NFT, NCONS = S::NCONS, NS = S::NS, NVERT = S::NVERT;
-    constexpr int NFACES = S::NFACES, NJS = MS::NJS, NRT = MS::NRT, NMS = MS::NMS;
+    constexpr int NFACES = S::NFACES, NJS = MS::NJS, NRT = Tiles<DIM, N, T>::NRT, NMS = MS::NMS;
     const int Nc = a.Nc;
     const int nct = (Nc + 15) / 16;
 
@@ -362,10 +382,10 @@ __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<DIM, N>(sizeof(T)))))
 stage_batch_kernel(BatchArgs<T> b, const BatchEntry<T> *__restrict__ ent) {
     using S = Shape<DIM, N>;
     using MS = MShape<DIM, N>;
-    using O = MOps<DIM, N>;
+    using O = MOps<DIM, N, T>;
     using V = typename Vec4<T>::type;
     constexpr int NP = S::NP, NF = S::NF, NCONS = S::NCONS, NS = S::NS, NVERT = S::NVERT;
-    constexpr int NFACES = S::NFACES, NJS = MS::NJS, NRT = MS::NRT, NMS = MS::NMS;
+    constexpr int NFACES = S::NFACES, NJS = MS::NJS, NRT = Tiles<DIM, N, T>::NRT, NMS = MS::NMS;
     const int Nc = b.Nc;
     const int nct = (Nc + 15) / 16;
 
