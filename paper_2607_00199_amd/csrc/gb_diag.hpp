@@ -150,6 +150,116 @@ __global__ void __launch_bounds__(kDiagBlock) energy_partial_kernel(EnergyArgs<T
     }
 }
 
+// The same sums (same per-lane order of points and terms) with the
+// interpolation rows of the lane's two cubature points (p = lane and
+// lane + 64, so Nc <= 128) held in registers for the whole launch instead of
+// read from LDS for every element; the order's node count NP is a template
+// parameter so that the rows stay in registers.
+template <int DIM, typename T, int NP>
+__global__ void __launch_bounds__(kDiagBlock) energy_partial_reg_kernel(EnergyArgs<T> a) {
+    constexpr int NC = DIM + 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *s_red = reinterpret_cast<double *>(smem);         // [blockDim]
+    double *s_q = s_red + blockDim.x;                          // per wave [2][NC][NP]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    double *q = s_q + wave * 2 * NC * NP;
+    double *f = q + NC * NP;
+    double Ir[2][NP], wc[2];
+    bool live[2];
+#pragma unroll
+    for (int pt = 0; pt < 2; ++pt) {
+        const int p = lane + 64 * pt;
+        live[pt] = p < a.Nc;
+        const int pc = live[pt] ? p : 0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) Ir[pt][j] = a.Icub[pc * NP + j];
+        wc[pt] = a.wcub[pc];
+    }
+    double acc[kDiagSums] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t stride = int64_t(gridDim.x) * waves;
+    for (int64_t e = int64_t(blockIdx.x) * waves + wave; e < a.K; e += stride) {
+        for (int p = lane; p < NC * NP; p += 64) {
+            const int k = p / NP, j = p - k * NP;
+            const int64_t off = (((e >> 4) * a.NF + k) * NP + j) * 16 + (e & 15);
+            q[p] = double(a.Q[off]) + (k == 0 ? a.rho0 : 0.0);
+            f[p] = double(a.F[off]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double xv[DIM + 1][DIM], wv[DIM + 1][DIM];
+        for (int v = 0; v <= DIM; ++v) {
+            const int64_t gv = a.etov[e * (DIM + 1) + v];
+            for (int d = 0; d < DIM; ++d) {
+                xv[v][d] = a.x[gv * DIM + d];
+                wv[v][d] = a.w[gv * DIM + d];
+            }
+        }
+        double G[DIM][DIM], Wr[DIM][DIM];
+        for (int i = 0; i < DIM; ++i)
+            for (int aa = 0; aa < DIM; ++aa) {
+                G[i][aa] = 0.5 * (xv[aa + 1][i] - xv[0][i]);
+                Wr[i][aa] = 0.5 * (wv[aa + 1][i] - wv[0][i]);
+            }
+        double J, divw = 0.0;
+        if constexpr (DIM == 2) {
+            J = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+            divw = (Wr[0][0] * G[1][1] - Wr[0][1] * G[1][0] - Wr[1][0] * G[0][1] + Wr[1][1] * G[0][0]) / J;
+        } else {
+            double C[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int aa = 0; aa < 3; ++aa) {
+                    const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, a1 = (aa + 1) % 3, a2 = (aa + 2) % 3;
+                    C[i][aa] = G[i1][a1] * G[i2][a2] - G[i1][a2] * G[i2][a1];
+                }
+            J = G[0][0] * C[0][0] + G[0][1] * C[0][1] + G[0][2] * C[0][2];
+            for (int i = 0; i < 3; ++i)
+                for (int aa = 0; aa < 3; ++aa) divw += Wr[i][aa] * C[i][aa];
+            divw /= J;
+        }
+        const double c2 = a.c * a.c;
+        double se = 0.0, sde = 0.0, sw = 0.0;
+#pragma unroll
+        for (int pt = 0; pt < 2; ++pt) {
+            if (!live[pt]) continue;
+            double v[NC], dv[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    s0 += Ir[pt][j] * q[k * NP + j];
+                    s1 += Ir[pt][j] * f[k * NP + j];
+                }
+                v[k] = s0;
+                dv[k] = s1;
+            }
+            double mm = 0.0, mdm = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                mm += v[1 + d] * v[1 + d];
+                mdm += v[1 + d] * dv[1 + d];
+            }
+            const double ir = 1.0 / v[0];
+            const double e_c = 0.5 * c2 * mm * ir;
+            const double de_c = c2 * mdm * ir - 0.5 * c2 * mm * dv[0] * ir * ir;
+            se += wc[pt] * e_c;
+            sde += wc[pt] * de_c;
+            sw += wc[pt];
+        }
+        acc[0] += J * se;
+        acc[1] += J * divw * se + J * sde;
+        acc[2] += J * sw;
+        acc[3] += J * divw * sw;
+        __builtin_amdgcn_wave_barrier();    // q, f reused by the wave's next element
+    }
+    for (int k = 0; k < kDiagSums; ++k) {
+        const double s = block_sum(acc[k], s_red);
+        if (threadIdx.x == 0) a.partial[int64_t(blockIdx.x) * kDiagSums + k] = s;
+    }
+}
+
 // Final pass (one workgroup): sums of the partials in a fixed order, then
 // out = {E_K, -dE_K/dt, |Omega|}.
 __global__ void __launch_bounds__(kDiagBlock) energy_final_kernel(const double *partial, int nblocks, double rho_inf,

@@ -1585,9 +1585,20 @@ int energy_grid(const gb_solver *s) {
                                                       (waves + per_block - 1) / per_block)));
 }
 
+// The register form of the energy kernel serves rules of up to 128 points
+// on the built orders (its node count is a template parameter).
+bool energy_in_registers(const gb_solver *s) {
+    const int Np = s->ref.Np;
+    const bool np_ok = s->mesh->dim == 2 ? (Np == 3 || Np == 6 || Np == 10 || Np == 15 || Np == 21)
+                                         : (Np == 4 || Np == 10 || Np == 20);
+    return s->ref.Nc <= 128 && np_ok;
+}
+
 size_t energy_lds(const gb_solver *s) {
     const int NC = s->mesh->dim + 1, Np = s->ref.Np, Nc = s->ref.Nc;
-    return sizeof(double) * (size_t(Nc) * Np + Nc + gbd::kDiagBlock + (gbd::kDiagBlock / 64) * 2 * NC * Np);
+    const size_t waves = gbd::kDiagBlock / 64;
+    if (energy_in_registers(s)) return sizeof(double) * (gbd::kDiagBlock + waves * 2 * NC * Np);
+    return sizeof(double) * (size_t(Nc) * Np + Nc + gbd::kDiagBlock + waves * 2 * NC * Np);
 }
 
 // Enqueue the energy diagnostic: the current geometry and grid velocity
@@ -1621,7 +1632,27 @@ gb_status enqueue_energy(gb_solver *s, const Launcher &L, double rho_inf, double
         a.c = s->prm.c;
         a.rho0 = rho0;
         a.partial = partial;
-        hipLaunchKernelGGL((gbd::energy_partial_kernel<D, T>), dim3(grid), dim3(gbd::kDiagBlock), lds, st, a);
+        auto reg = [&](auto npc) {
+            constexpr int NP = decltype(npc)::value;
+            hipLaunchKernelGGL((gbd::energy_partial_reg_kernel<D, T, NP>), dim3(grid), dim3(gbd::kDiagBlock), lds, st, a);
+        };
+        if (energy_in_registers(s)) {
+            if constexpr (D == 2) {
+                switch (a.Np) {
+                    case 3: reg(std::integral_constant<int, 3>{}); break;
+                    case 6: reg(std::integral_constant<int, 6>{}); break;
+                    case 10: reg(std::integral_constant<int, 10>{}); break;
+                    case 15: reg(std::integral_constant<int, 15>{}); break;
+                    default: reg(std::integral_constant<int, 21>{}); break;
+                }
+            } else {
+                switch (a.Np) {
+                    case 4: reg(std::integral_constant<int, 4>{}); break;
+                    case 10: reg(std::integral_constant<int, 10>{}); break;
+                    default: reg(std::integral_constant<int, 20>{}); break;
+                }
+            }
+        } else hipLaunchKernelGGL((gbd::energy_partial_kernel<D, T>), dim3(grid), dim3(gbd::kDiagBlock), lds, st, a);
         return hipGetLastError();
     };
     hipError_t e;
