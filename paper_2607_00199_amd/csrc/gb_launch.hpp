@@ -89,8 +89,10 @@ hipError_t launch_stage(const LaunchArgs &L, int kind, hipStream_t st) {
     a.K = L.K;
     a.nbatch = int((L.K + 15) / 16);          // groups of 16 elements (one per wavefront)
     a.Nc = L.Nc;
-    // each workgroup (kWaves wavefronts) takes a contiguous range of groups
-    int grid = std::min(L.grid, (a.nbatch + kWaves - 1) / kWaves);
+    // each workgroup (W wavefronts) takes a contiguous range of groups, or
+    // blocks of W groups round robin; L.grid counts 4-wavefront workgroups
+    constexpr int W = stage_wg_waves<DIM, N, T>();
+    int grid = std::min(L.grid * kWaves / W, (a.nbatch + W - 1) / W);
     if (grid >= 8) grid = grid / 8 * 8;
     a.chunk = (a.nbatch + grid - 1) / grid;
     grid = (a.nbatch + a.chunk - 1) / a.chunk;
@@ -114,7 +116,7 @@ hipError_t launch_stage(const LaunchArgs &L, int kind, hipStream_t st) {
     a.clock = L.clock;
     a.kc = static_cast<const KConst<T> *>(L.kc);
     a.err = L.err;
-    const dim3 block(64 * kWaves);
+    const dim3 block(64 * W);
     using K0 = decltype(&stage_mfma_kernel<DIM, N, T, 0>);
     const K0 fns[5] = {&stage_mfma_kernel<DIM, N, T, 0>, &stage_mfma_kernel<DIM, N, T, 1>,
                        &stage_mfma_kernel<DIM, N, T, 2>, &stage_mfma_kernel<DIM, N, T, 3>,
@@ -218,7 +220,7 @@ template <int DIM, int N, typename T>
 size_t stage_batch_lds(int Nc, int nreq, int waves) { return batch_lds_bytes<DIM, N, T>((Nc + 15) / 16, nreq, waves); }
 
 template <int DIM, int N, typename T>
-size_t stage_lds(int Nc) { return mfma_lds_bytes<DIM, N, T>((Nc + 15) / 16); }
+size_t stage_lds(int Nc) { return mfma_lds_bytes<DIM, N, T>((Nc + 15) / 16, stage_wg_waves<DIM, N, T>()); }
 
 template <int DIM, int N, typename T>
 int stage_ops_total(int Nc) { return MOps<DIM, N, T>::total((Nc + 15) / 16); }

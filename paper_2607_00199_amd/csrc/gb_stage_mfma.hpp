@@ -245,9 +245,19 @@ __host__ __device__ constexpr int stage_waves_per_eu(int elem_bytes) {
     return (elem_bytes == 4 && DIM == 2 && MShape<DIM, N>::NRT == 1) ? 2 : 1;
 }
 
+// Wavefronts per workgroup of the single-mesh stage kernel: kernels at two
+// wavefronts per SIMD run one 8-wavefront workgroup per CU, which stages the
+// operator fragments in LDS once for all eight (measured 2.6 % faster on the
+// 2D TGV than two 4-wavefront workgroups per CU); the others run
+// 4-wavefront workgroups, two per CU.
+template <int DIM, int N, typename T>
+__host__ __device__ constexpr int stage_wg_waves() {
+    return stage_waves_per_eu<DIM, N>(sizeof(T)) >= 2 ? 2 * kWaves : kWaves;
+}
+
 template <int DIM, int N, typename T, int STAGE>
-__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<DIM, N>(sizeof(T)))))
-stage_mfma_kernel(KArgs<T> a) {
+__global__ void __launch_bounds__((64 * stage_wg_waves<DIM, N, T>()))
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<DIM, N>(sizeof(T))))) stage_mfma_kernel(KArgs<T> a) {
     using S = Shape<DIM, N>;
     using MS = MShape<DIM, N>;
     using O = MOps<DIM, N, T>;
