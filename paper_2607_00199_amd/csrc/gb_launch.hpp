@@ -16,7 +16,7 @@ struct LaunchArgs {
     int64_t K = 0;
     int64_t nv = 0;
     int Nc = 0;
-    int grid = 1;              // workgroups for a full chip (CUs x 8)
+    int grid = 1;              // workgroups for a full chip (one per CU)
     bool interleave = false;   // groups dealt to workgroups round robin instead of in ranges
     size_t lds = 0;            // dynamic LDS bytes per workgroup
     const int32_t *etov = nullptr;
@@ -90,9 +90,9 @@ hipError_t launch_stage(const LaunchArgs &L, int kind, hipStream_t st) {
     a.nbatch = int((L.K + 15) / 16);          // groups of 16 elements (one per wavefront)
     a.Nc = L.Nc;
     // each workgroup (W wavefronts) takes a contiguous range of groups, or
-    // blocks of W groups round robin; L.grid counts 4-wavefront workgroups
+    // blocks of W groups round robin
     constexpr int W = stage_wg_waves<DIM, N, T>();
-    int grid = std::min(L.grid * kWaves / W, (a.nbatch + W - 1) / W);
+    int grid = std::min(L.grid, (a.nbatch + W - 1) / W);
     if (grid >= 8) grid = grid / 8 * 8;
     a.chunk = (a.nbatch + grid - 1) / grid;
     grid = (a.nbatch + a.chunk - 1) / a.chunk;

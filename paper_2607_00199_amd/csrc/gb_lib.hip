@@ -1260,14 +1260,16 @@ gb_status gb_solver_create(gb_mesh *m, const gb_params *p, gb_solver **out) {
     if (need > m->ctx->max_lds) return fail(GB_ERR_UNSUPPORTED, "reference operators exceed the LDS of one workgroup");
     s->lds = need;
     s->kconst_host.assign(std::max(sizeof(gbd::KConst<double>), sizeof(gbd::KConst<float>)), 0);
-    // two workgroups per CU, each persistent over a contiguous range of
-    // element groups (the operator fragments are staged in LDS once per
-    // workgroup); measured faster than one workgroup per group
-    s->grid = m->ctx->num_cu * 2;
+    // one persistent workgroup per CU (4 or 8 wavefronts, as the kernel's
+    // occupancy allows), so the operator fragments are staged in LDS once per
+    // CU; measured faster than one workgroup per group, and than two
+    // workgroups per CU (3D TGV 1.385 -> 1.309 ms, 2D FP64 152.5 -> 149.0 us)
+    s->grid = m->ctx->num_cu;
     // Tetrahedra deal their groups round robin: the groups in flight then form
     // one contiguous window, so face neighbours a few cube rows away are
-    // gathered while still in L2 (measured 3.8 % faster on the 3D TGV); on
-    // the triangle workloads both dealings measured the same.
+    // gathered while still in L2 (measured 3.8 % faster on the 3D TGV before
+    // stage 1 read a single array; equal since); on the triangle workloads
+    // both dealings measured the same.
     s->interleave = m->dim == 3;
     GB_HIP(hipSetDevice(m->ctx->device));
     const size_t n = size_t((m->K + 15) / 16 * 16) * s->NF * Np;   // padded to whole groups of 16

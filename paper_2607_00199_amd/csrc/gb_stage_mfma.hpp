@@ -245,11 +245,10 @@ __host__ __device__ constexpr int stage_waves_per_eu(int elem_bytes) {
     return (elem_bytes == 4 && DIM == 2 && MShape<DIM, N>::NRT == 1) ? 2 : 1;
 }
 
-// Wavefronts per workgroup of the single-mesh stage kernel: kernels at two
-// wavefronts per SIMD run one 8-wavefront workgroup per CU, which stages the
-// operator fragments in LDS once for all eight (measured 2.6 % faster on the
-// 2D TGV than two 4-wavefront workgroups per CU); the others run
-// 4-wavefront workgroups, two per CU.
+// Wavefronts per workgroup of the single-mesh stage kernel, which runs one
+// workgroup per CU: eight for kernels at two wavefronts per SIMD (measured
+// 2.6 % faster on the 2D TGV than two 4-wavefront workgroups per CU), four
+// for the others.
 template <int DIM, int N, typename T>
 __host__ __device__ constexpr int stage_wg_waves() {
     return stage_waves_per_eu<DIM, N>(sizeof(T)) >= 2 ? 2 * kWaves : kWaves;
