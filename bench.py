@@ -33,13 +33,15 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per stage launch of the FP32 2D N=4 stage kernel at 131072
 # triangles, from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by kernels of
 # known size (profiles/stage_kernel_c2_256_n4_mfma.md).  Reported only while
-# the kernel sources still hash to the digest they were measured with.
+# the kernel and launch sources still hash to the digest they were measured
+# with.
 MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
-                "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp"],
-    "sha256": "eb1eef62f88d8a10933a4d979d572cdc1b17b0b1d85a678bb8d9849ce7834221",
+                "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp",
+                "paper_2607_00199_amd/csrc/gb_launch.hpp"],
+    "sha256": "6fcd6a4bd9b6ac5a38a20e13fef1a16c20383eb50a26b84af9106613e4c3e2f3",
     "K": 131072,
-    "bytes_per_launch": 205461 * 1024,
+    "bytes_per_launch": 198248 * 1024,
 }
 
 
