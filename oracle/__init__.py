@@ -16,7 +16,10 @@ anything the paper or mathematics fixes say "parity unpinned" in their
 docstring.
 
 Parity-unpinned parts (see the individual docstrings):
-  * the 3D 10-field moment system (the paper only cites it) beyond its 2D
+  * the 3D 10-field moment system as a model of the paper's 3D runs (the
+    paper only cites it; the tensor form taken restricts to the printed 2D
+    system).  Its discretisation here is pinned to that tensor form by
+    convergence against an independent spectral solution, and by its 2D
     restriction, spectrum, conservation and covariance.
 The wall / far-field ghost states and the sponge layer are stand-ins for the
 paper's wall treatment and perfectly matched layer, which it names without

@@ -12,7 +12,10 @@
   * Convergence of the moving-mesh solution at order >= N + 0.7 for
     N = 2, 3, 4 on 8^2, 16^2, 32^2 quads against the Fourier pseudo-spectral
     solution of the continuous system, with the mass integral kept to
-    rounding on the moving mesh.
+    rounding on the moving mesh; in 3D, convergence of the moving tetrahedral
+    solution to the spectral solution of the tensor-form system (written
+    without the oracle's flux matrices) on the coarse meshes a CPU test
+    affords.
 """
 import math
 import os
@@ -27,6 +30,7 @@ from oracle.motion import Motion, stage_positions
 from oracle.rhs import Params, rhs
 from oracle.solver import Solver
 from workloads import kuhn_cube, ogrid_airfoil, periodic_square, taylor_green_2d
+from workloads.fields import taylor_green_3d
 from workloads.configs import cfl_dt
 
 FISH = dict(a0=0.02, a1=-0.08, a2=0.16, lam=1.0, f=1.0, R_rigid=0.5, beta=10.0, T_ramp=1.0)
@@ -294,3 +298,49 @@ def test_moving_mesh_convergence_order_n_plus_one():
         assert min(rates) > N, (N, errs, rates)
         for n in (8, 16, 32):
             assert res[(N, n)][1] < 1e-13, (N, n, res[(N, n)][1])
+
+
+_CONV3_T, _CONV3_TAU, _CONV3_U0 = 0.2, 0.05, 0.2
+
+
+def _conv_errors_3d(args):
+    """Relative L2 error at t = 0.2 of one (N, cubes per side) 3D run on
+    [-pi, pi]^3 (Kuhn tetrahedra, triple-product motion) against the 3D
+    spectral solution; executed in a worker process."""
+    from tests.spectral_ref import Spectral3D
+    N, n = args
+    vx, etov, per, _ = kuhn_cube(n)
+    s = Solver(Mesh(3, N, vx, etov, per), Params(c=1.0, tau=_CONV3_TAU),
+               Motion("triple_product_3d", A=0.02, T=1.0, L=2 * math.pi))
+    X = s.node_coords()
+    rho, u = taylor_green_3d(X[:, 0], X[:, 1], X[:, 2], _CONV3_U0)
+    s.set_state(gb.equilibrium(3, rho, u, 1.0).transpose(1, 0, 2))
+    nst = int(math.ceil(_CONV3_T / cfl_dt(vx, etov, N, 1.0, 1.0, 0.25)))
+    s.run(_CONV3_T / nst, nst)
+    sp = Spectral3D(16, 1.0, _CONV3_TAU)
+    Z, Y, Xs = np.meshgrid(sp.x, sp.x, sp.x, indexing="ij")
+    rho, u = taylor_green_3d(Xs, Y, Z, _CONV3_U0)
+    qT = sp.solve(gb.equilibrium(3, rho, u, 1.0), _CONV3_T)
+    X = s.node_coords()
+    ref = sp.evaluate(qT, X[:, 0], X[:, 1], X[:, 2]).transpose(1, 0, 2)
+    err = s.l2_norm(s.q - ref)
+    nrm = s.l2_norm(ref)
+    return float(np.sqrt((err ** 2).sum()) / np.sqrt((nrm[1:4] ** 2).sum()))
+
+
+def test_moving_mesh_convergence_3d():
+    """The 3D moving-mesh solution converges to the continuous tensor-form
+    system: N = 3 on 4^3 -> 8^3 cubes at order > 3.3 (observed 3.65), and,
+    on coarser meshes, N = 1 (4^3 -> 8^3) and N = 2 (2^3 -> 4^3) at orders
+    > 1.5 and > 2.0 (observed 1.62 and 2.22; k h = 1.6 and 0.8 per cube for
+    the k = 1 vortex, pre-asymptotic).  The N = 3 pair resolves the model:
+    dropping one flux-matrix entry (m_y through d_x S_xy) in a copy of the
+    oracle leaves a 1.2 % error at 8^3 and an observed order of 0.85."""
+    cases = [(3, 8), (1, 8), (3, 4), (1, 4), (2, 4), (2, 2)]       # longest first
+    workers = max(1, min(6, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        res = dict(zip(cases, ex.map(_conv_errors_3d, cases)))
+    for N, (a, b), floor in ((1, (4, 8), 1.5), (2, (2, 4), 2.0), (3, (4, 8), 3.3)):
+        rate = math.log2(res[(N, a)] / res[(N, b)])
+        assert rate > floor, (N, res, rate)
+        assert res[(N, b)] < 0.25, (N, res)
