@@ -351,7 +351,8 @@ std::vector<T> pack_ops(const gbh::RefElement &R, std::vector<int32_t> &slot_tab
             for (int st = 0; st < NJS; ++st)
                 frag([&](int c, int q) { return at(R.D[a], row(rt, c), 4 * st + q); });
     for (int rt = 0; rt < NRT; ++rt)
-        for (int st = 0; st < NMS; ++st) frag([&](int c, int q) { return at(R.LIFT, row(rt, c), 4 * st + q); });
+        for (int st = 0; st < NMS; ++st)
+            frag([&](int c, int q) { return at(R.LIFT, row(rt, c), gbh::slot_face_node(R, 4 * st + q)); });
     // a thin last cubature tile (at most four real points, FP32): 4x4x1
     // interpolation rows 16 t + c % 4, projection over points 16 t + q in slot 0
     const bool thin_c = gbd::thin_cub_tile(Nc, f32);
@@ -371,8 +372,9 @@ std::vector<T> pack_ops(const gbh::RefElement &R, std::vector<int32_t> &slot_tab
         for (int v = 0; v < nvert; ++v) o.push_back(T(R.bary(i, v)));
     slot_table.assign(size_t(4 * NMS) * 2, -1);
     for (int mm = 0; mm < NFT; ++mm) {
-        slot_table[2 * mm] = R.fmask[mm];
-        slot_table[2 * mm + 1] = mm / R.Nfp;
+        const int fn = gbh::slot_face_node(R, mm);
+        slot_table[2 * mm] = R.fmask[fn];
+        slot_table[2 * mm + 1] = fn / R.Nfp;
     }
     return o;
 }

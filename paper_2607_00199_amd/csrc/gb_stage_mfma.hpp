@@ -142,13 +142,15 @@ struct MShape {
 
 // Packed operator fragments (type T, 64 lane-ordered values per fragment):
 //   FD [DIM][NRT][NJS]   lane (q, c): D_a(row(rt, c), 4 s + q)
-//   FL [NRT][NMS]        LIFT(row(rt, c), 4 s + q)
+//   FL [NRT][NMS]        LIFT(row(rt, c), fn(4 s + q))
 //   FI [NCT][NJS]        Icub(16 t + c, 4 s + q)
 //   FP [NRT][NCT][4]     Pcub(row(rt, c), 16 t + crow(q, r))
 //   BARY [NP][NVERT]
 // with row(rt, c) = 16 rt + c on a 16-row tile and tile_row0(rt) + c % 4 on a
 // thin one (NRT counts both kinds), then an int table SLOT [4 NMS][2]:
-// (volume node, face) of face slot m, or -1.
+// (volume node, face) of face slot m, or -1.  fn(m) is the face node of slot
+// m: face m % 4, node m / 4 on tetrahedra, so the lanes of quarter q of an
+// element hold face q in every step; the face-node order on triangles.
 template <int DIM, int N, typename T>
 struct MOps {
     using M = MShape<DIM, N>;

@@ -701,7 +701,8 @@ std::vector<int32_t> blocked_trace_map(const RefElement &ref, int64_t K, const C
     const int64_t G = (K + 15) / 16;
     std::vector<int32_t> blk(size_t(G) * slots * 16, -3);
     for (int64_t e = 0; e < K; ++e)
-        for (int m = 0; m < NFT; ++m) blk[((e >> 4) * slots + m) * 16 + (e & 15)] = conn.vmapP[e * NFT + m];
+        for (int m = 0; m < NFT; ++m)
+            blk[((e >> 4) * slots + m) * 16 + (e & 15)] = conn.vmapP[e * NFT + slot_face_node(ref, m)];
     return blk;
 }
 
@@ -744,7 +745,7 @@ std::string check_mesh_tables(const RefElement &ref, int64_t nv, int64_t K, cons
             for (int l = 0; l < 16; ++l) {
                 const int64_t e = g * 16 + l;
                 const int32_t got = blocked[(g * slots + m) * 16 + l];
-                const int32_t want = (e < K && m < NFT) ? conn.vmapP[e * NFT + m] : -3;
+                const int32_t want = (e < K && m < NFT) ? conn.vmapP[e * NFT + slot_face_node(ref, m)] : -3;
                 if (got != want) return "blocked trace map differs from the flat one at group " + std::to_string(g);
             }
     return std::string();

@@ -57,9 +57,22 @@ Connectivity build_connectivity(const RefElement &ref, int64_t nv, const double 
                                 const int32_t *etov, const double *period, const int8_t *face_tag,
                                 std::string &err);
 
+// Face-node index (f*Nfp + i) held by kernel face slot m.  The stage kernel
+// gives slot 4 s + q to the lanes of quarter q of an element at step s.  On
+// tetrahedra (four faces) slot m holds face m % 4, node m / 4, so each lane
+// quarter keeps one face for all its steps; on triangles slots follow the
+// face-node order.  Slots at or past Nfaces*Nfp are padding and map to
+// themselves.
+inline int slot_face_node(const RefElement &ref, int m) {
+    const int nft = ref.Nfaces * ref.Nfp;
+    if (m >= nft || ref.Nfaces != 4) return m;
+    return (m % 4) * ref.Nfp + m / 4;
+}
+
 // Trace map in the device's blocked layout [ceil(K/16)][slots][16] (slots =
-// Nfaces*Nfp rounded up to 4): the exterior node of face node m of element e,
-// or -1 (wall), -2 (far field), -3 (padding of the last group or slot).
+// Nfaces*Nfp rounded up to 4): the exterior node of the face node in kernel
+// slot m (slot_face_node) of element e, or -1 (wall), -2 (far field), -3
+// (padding of the last group or slot).
 std::vector<int32_t> blocked_trace_map(const RefElement &ref, int64_t K, const Connectivity &conn);
 
 // Consistency of the device tables of a mesh, checked on the host: every
