@@ -39,9 +39,9 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp",
                 "paper_2607_00199_amd/csrc/gb_launch.hpp"],
-    "sha256": "6fcd6a4bd9b6ac5a38a20e13fef1a16c20383eb50a26b84af9106613e4c3e2f3",
+    "sha256": "149ceac6507edf2de0c930124eea602cbe37bcb349784aafe40f23541c9e16d6",
     "K": 131072,
-    "bytes_per_launch": 198248 * 1024,
+    "bytes_per_launch": 198165 * 1024,
 }
 
 
