@@ -713,6 +713,12 @@ std::string check_mesh_tables(const RefElement &ref, int64_t nv, int64_t K, cons
     const int64_t G = (K + 15) / 16;
     if (int64_t(conn.vmapP.size()) != K * NFT) return "trace map has the wrong size";
     if (int64_t(blocked.size()) != G * slots * 16) return "blocked trace map has the wrong size";
+    // the kernel's face-slot order visits every face node once
+    std::vector<char> seen(size_t(NFT), 0);
+    for (int m = 0; m < NFT; ++m) {
+        const int fn = slot_face_node(ref, m);
+        if (fn < 0 || fn >= NFT || seen[size_t(fn)]++) return "face-slot order is not a permutation of the face nodes";
+    }
     for (int64_t e = 0; e < K; ++e)
         for (int v = 0; v < nvert; ++v) {
             const int32_t gv = etov[e * nvert + v];

@@ -77,8 +77,9 @@ std::vector<int32_t> blocked_trace_map(const RefElement &ref, int64_t K, const C
 
 // Consistency of the device tables of a mesh, checked on the host: every
 // trace-map entry is a boundary code or a node of another element's face,
-// the map is an involution on matched faces, the blocked copy equals the
-// flat one with padding where no element or slot exists, and every element's
+// the map is an involution on matched faces, the face-slot order is a
+// permutation of the face nodes, the blocked copy equals the flat one in that
+// order with padding where no element or slot exists, and every element's
 // vertex ids are in range.  Returns an empty string or the first violation.
 std::string check_mesh_tables(const RefElement &ref, int64_t nv, int64_t K, const int32_t *etov,
                               const Connectivity &conn, const std::vector<int32_t> &blocked);

@@ -4,8 +4,9 @@
     builds for a mesh (periodic squares at every triangle order including
     N = 5, Kuhn cubes at every tetrahedron order, a walled O-grid, a
     tetrahedral box with far-field faces all round) have every index in
-    range, are involutions on matched faces, and the blocked copy equals the
-    flat one;
+    range, are involutions on matched faces, the kernel's face-slot order
+    (one face per lane quarter on tetrahedra) is a permutation of the face
+    nodes, and the blocked copy equals the flat one in that order;
   * gb_check_batch_layout: the request-table layout of a batched launch class
     (members of the served mix's sizes, including the triangle order-5 FP64
     shape the batched form refuses) passes the checks the batch runs before
