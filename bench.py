@@ -342,7 +342,7 @@ def main():
     ap.add_argument("--series-every", type=int, default=25)
     ap.add_argument("--no-served", action="store_true",
                     help="skip the bounded served run appended to the default line")
-    ap.add_argument("--served-requests-default", type=int, default=16,
+    ap.add_argument("--served-requests-default", type=int, default=64,
                     help="requests of the bounded served run on the default line")
     ap.add_argument("--served-steps-default", type=int, default=1000,
                     help="steps per request of the bounded served run on the default line")
