@@ -39,9 +39,9 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp",
                 "paper_2607_00199_amd/csrc/gb_launch.hpp"],
-    "sha256": "01b0a1f8fce6125f2a9083f7e0f54a9f6b4aad02cf5d53a302536917d6c6016d",
+    "sha256": "0e7050c5b10b108957852844cc47826b0f6b323263da42260cd541b31f9668a6",
     "K": 131072,
-    "bytes_per_launch": 198168 * 1024,
+    "bytes_per_launch": 198300 * 1024,
 }
 
 

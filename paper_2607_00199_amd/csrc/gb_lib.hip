@@ -419,8 +419,8 @@ hipError_t ensure_consts(gb_solver *s, const Launcher &L, hipStream_t st) {
 
 hipError_t launch_motion(gb_solver *s, double dt, hipStream_t st) {
     gb_mesh *m = s->mesh;
-    const int blk = 256;
-    const unsigned nb = unsigned((m->nv + blk - 1) / blk);
+    const int blk = 256;   // four lanes per vertex
+    const unsigned nb = unsigned((4 * m->nv + blk - 1) / blk);
     if (m->dim == 2)
         hipLaunchKernelGGL(gbd::motion_stages_kernel<2>, dim3(nb), dim3(blk), 0, st, m->nv, m->d_X.as<double>(),
                            m->d_x.as<double>(), s->clock.as<double>(), dt, m->motion, s->vstage.as<double>(),

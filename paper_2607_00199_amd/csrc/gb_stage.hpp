@@ -139,12 +139,50 @@ __device__ __forceinline__ void motion_vertex(int64_t v, int64_t nv, const doubl
     }
 }
 
+// The same per vertex, spread over four lanes, one per stage: the velocity
+// evaluations at the stage times are independent, so lane j (of the four
+// consecutive lanes of vertex v) evaluates w_j, writes it and the stage
+// position that starts from it (x_n + c_{j+1} dt w_j for j < 3), and the
+// lane of stage 3 takes w_0..w_2 from the other three for x_{n+1}.  The
+// arithmetic is that of motion_vertex; launched with 4 nv threads in blocks
+// of a multiple of 64.
 template <int DIM>
 __global__ void motion_stages_kernel(int64_t nv, const double *X, const double *x, const double *clock, double dt,
                                      Motion m, double *xs, double *ws) {
-    const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
-    motion_vertex<DIM>(v, nv, X, x, clock[0], dt, m, xs, ws);
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t v = tid >> 2;
+    const int j = int(tid & 3);
+    const bool live = v < nv;
+    // lanes past the last vertex compute vertex nv - 1 and store nothing, so
+    // every lane of a vertex takes part in the exchanges below
+    const int64_t vc = live ? v : nv - 1;
+    const double tn = clock[0];
+    const int64_t st = nv * DIM;
+    double Xv[DIM], xn[DIM], w[DIM];
+    for (int d = 0; d < DIM; ++d) {
+        Xv[d] = X[vc * DIM + d];
+        xn[d] = x[vc * DIM + d];
+    }
+    if (m.kind == 4) {
+        for (int d = 0; d < DIM; ++d) w[d] = m.w[j * st + vc * DIM + d];
+    } else {
+        motion_velocity<DIM>(m, Xv, tn + (j == 0 ? 0.0 : j == 3 ? 1.0 : 0.5) * dt, w);
+    }
+    const int base = int(threadIdx.x & 63) & ~3;
+    double w0[DIM], w1[DIM], w2[DIM];
+    for (int d = 0; d < DIM; ++d) {
+        w0[d] = __shfl(w[d], base + 0);
+        w1[d] = __shfl(w[d], base + 1);
+        w2[d] = __shfl(w[d], base + 2);
+    }
+    if (!live) return;
+    for (int d = 0; d < DIM; ++d) {
+        const int64_t o = v * DIM + d;
+        ws[j * st + o] = w[d];
+        if (j == 0) xs[o] = xn[d];
+        if (j < 3) xs[(j + 1) * st + o] = xn[d] + (j == 2 ? 1.0 : 0.5) * dt * w[d];
+        if (j == 3) xs[4 * st + o] = xn[d] + dt * (w0[d] + 2.0 * w1[d] + 2.0 * w2[d] + w[d]) / 6.0;
+    }
 }
 
 // End of a step: x_n <- x_{n+1}; the first thread also advances the clock.
