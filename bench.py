@@ -39,9 +39,9 @@ MEASURED_TRAFFIC = {
     "sources": ["paper_2607_00199_amd/csrc/gb_stage_mfma.hpp", "paper_2607_00199_amd/csrc/gb_stage_body.inc",
                 "paper_2607_00199_amd/csrc/gb_stage.hpp", "paper_2607_00199_amd/csrc/gb_device.hpp",
                 "paper_2607_00199_amd/csrc/gb_launch.hpp"],
-    "sha256": "0e7050c5b10b108957852844cc47826b0f6b323263da42260cd541b31f9668a6",
+    "sha256": "aa6654e126d360d89cff62b514f879b54946cb867177e9801faa058f91c66f1d",
     "K": 131072,
-    "bytes_per_launch": 198300 * 1024,
+    "bytes_per_launch": 198233 * 1024,
 }
 
 

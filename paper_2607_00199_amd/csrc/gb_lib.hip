@@ -616,7 +616,8 @@ hipError_t launch_vertex_batch(gb_batch *b, int set, bool finish, hipStream_t st
     const gb_batch::VertexSet &vs = b->vsets[size_t(set)];
     if (vs.n == 0) return hipSuccess;
     const int blk = 256;
-    const unsigned nb = unsigned((vs.vtot + blk - 1) / blk);
+    // the motion kernel runs four lanes per vertex
+    const unsigned nb = unsigned(((finish ? 1 : 4) * vs.vtot + blk - 1) / blk);
     const gbd::MotionEntry *E = b->mot.as<gbd::MotionEntry>() + vs.first;
     if (vs.dim == 2) {
         if (finish)
@@ -638,7 +639,7 @@ hipError_t node_vertex_batch(gb_batch *b, int set, bool finish, gbd::GraphAppend
     const gb_batch::VertexSet &vs = b->vsets[size_t(set)];
     if (vs.n == 0) return hipSuccess;
     const int blk = 256;
-    const unsigned nb = unsigned((vs.vtot + blk - 1) / blk);
+    const unsigned nb = unsigned(((finish ? 1 : 4) * vs.vtot + blk - 1) / blk);
     const gbd::MotionEntry *E = b->mot.as<gbd::MotionEntry>() + vs.first;
     int n = vs.n;
     int64_t vtot = vs.vtot;

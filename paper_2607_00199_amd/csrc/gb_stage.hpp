@@ -101,70 +101,25 @@ __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 //   x_{n+1} = x_n + dt (w(t_n) + 2 w(t_n+dt/2) + 2 w(t_n+dt/2) + w(t_n+dt)) / 6
 // and stage j uses the velocity w(t_n + c_j dt), c = (0, 1/2, 1/2, 1).
 // Writes xs[s][nv][DIM] for s = 0..4 (4 = end of step) and ws[s][nv][DIM]
-// for s = 0..3.
+// for s = 0..3.  The stage velocities are independent, so the work of a
+// vertex is spread over four consecutive lanes, one per stage: lane j
+// evaluates w_j, writes it and the stage position that starts from it
+// (x_n + c_{j+1} dt w_j for j < 3; lane 0 also writes x_n0), and lane 3 takes
+// w_0..w_2 from the other three for x_{n+1}.  All four lanes of a vertex must
+// be active; a lane with live false computes and takes part in the exchange
+// but stores nothing.
 template <int DIM>
-__device__ __forceinline__ void motion_vertex(int64_t v, int64_t nv, const double *X, const double *x, double tn,
-                                              double dt, const Motion &m, double *xs, double *ws) {
-    double Xv[DIM], xn[DIM], w0[DIM], w1[DIM], w2[DIM], w3[DIM];
+__device__ __forceinline__ void motion_vertex_lanes(int64_t v, int j, bool live, int64_t nv, const double *X,
+                                                    const double *x, double tn, double dt, const Motion &m,
+                                                    double *xs, double *ws) {
+    const int64_t st = nv * DIM;
+    double Xv[DIM], xn[DIM], w[DIM];
     for (int d = 0; d < DIM; ++d) {
         Xv[d] = X[v * DIM + d];
         xn[d] = x[v * DIM + d];
     }
     if (m.kind == 4) {
-        const int64_t st = nv * DIM;
-        for (int d = 0; d < DIM; ++d) {
-            w0[d] = m.w[0 * st + v * DIM + d];
-            w1[d] = m.w[1 * st + v * DIM + d];
-            w2[d] = m.w[2 * st + v * DIM + d];
-            w3[d] = m.w[3 * st + v * DIM + d];
-        }
-    } else {
-        motion_velocity<DIM>(m, Xv, tn, w0);
-        motion_velocity<DIM>(m, Xv, tn + 0.5 * dt, w1);
-        motion_velocity<DIM>(m, Xv, tn + 0.5 * dt, w2);
-        motion_velocity<DIM>(m, Xv, tn + 1.0 * dt, w3);
-    }
-    const int64_t st = nv * DIM;
-    for (int d = 0; d < DIM; ++d) {
-        const int64_t o = v * DIM + d;
-        xs[0 * st + o] = xn[d];
-        xs[1 * st + o] = xn[d] + 0.5 * dt * w0[d];
-        xs[2 * st + o] = xn[d] + 0.5 * dt * w1[d];
-        xs[3 * st + o] = xn[d] + dt * w2[d];
-        xs[4 * st + o] = xn[d] + dt * (w0[d] + 2.0 * w1[d] + 2.0 * w2[d] + w3[d]) / 6.0;
-        ws[0 * st + o] = w0[d];
-        ws[1 * st + o] = w1[d];
-        ws[2 * st + o] = w2[d];
-        ws[3 * st + o] = w3[d];
-    }
-}
-
-// The same per vertex, spread over four lanes, one per stage: the velocity
-// evaluations at the stage times are independent, so lane j (of the four
-// consecutive lanes of vertex v) evaluates w_j, writes it and the stage
-// position that starts from it (x_n + c_{j+1} dt w_j for j < 3), and the
-// lane of stage 3 takes w_0..w_2 from the other three for x_{n+1}.  The
-// arithmetic is that of motion_vertex; launched with 4 nv threads in blocks
-// of a multiple of 64.
-template <int DIM>
-__global__ void motion_stages_kernel(int64_t nv, const double *X, const double *x, const double *clock, double dt,
-                                     Motion m, double *xs, double *ws) {
-    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t v = tid >> 2;
-    const int j = int(tid & 3);
-    const bool live = v < nv;
-    // lanes past the last vertex compute vertex nv - 1 and store nothing, so
-    // every lane of a vertex takes part in the exchanges below
-    const int64_t vc = live ? v : nv - 1;
-    const double tn = clock[0];
-    const int64_t st = nv * DIM;
-    double Xv[DIM], xn[DIM], w[DIM];
-    for (int d = 0; d < DIM; ++d) {
-        Xv[d] = X[vc * DIM + d];
-        xn[d] = x[vc * DIM + d];
-    }
-    if (m.kind == 4) {
-        for (int d = 0; d < DIM; ++d) w[d] = m.w[j * st + vc * DIM + d];
+        for (int d = 0; d < DIM; ++d) w[d] = m.w[j * st + v * DIM + d];
     } else {
         motion_velocity<DIM>(m, Xv, tn + (j == 0 ? 0.0 : j == 3 ? 1.0 : 0.5) * dt, w);
     }
@@ -183,6 +138,17 @@ __global__ void motion_stages_kernel(int64_t nv, const double *X, const double *
         if (j < 3) xs[(j + 1) * st + o] = xn[d] + (j == 2 ? 1.0 : 0.5) * dt * w[d];
         if (j == 3) xs[4 * st + o] = xn[d] + dt * (w0[d] + 2.0 * w1[d] + 2.0 * w2[d] + w[d]) / 6.0;
     }
+}
+
+// One mesh: 4 nv threads in blocks of a multiple of 64; lanes past the last
+// vertex compute vertex nv - 1 and store nothing.
+template <int DIM>
+__global__ void motion_stages_kernel(int64_t nv, const double *X, const double *x, const double *clock, double dt,
+                                     Motion m, double *xs, double *ws) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t v = tid >> 2;
+    const bool live = v < nv;
+    motion_vertex_lanes<DIM>(live ? v : nv - 1, int(tid & 3), live, nv, X, x, clock[0], dt, m, xs, ws);
 }
 
 // End of a step: x_n <- x_{n+1}; the first thread also advances the clock.
@@ -234,12 +200,15 @@ __global__ void motion_batch_kernel(const MotionEntry *E, int n, int64_t total) 
     __shared__ int64_t s_vb[kMaxBatch];
     for (int p = threadIdx.x; p < n; p += blockDim.x) s_vb[p] = E[p].v_begin;
     __syncthreads();
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    // four lanes per vertex (motion_vertex_lanes); the four lanes of a vertex
+    // leave together or not at all
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = tid >> 2;
     if (i >= total) return;
     const MotionEntry &e = E[table_search(s_vb, n, i)];
     if (e.clock[1] >= e.target) return;
-    const int64_t v = i - e.v_begin;
-    motion_vertex<DIM>(v, e.nv, e.X, e.x, e.clock[0], e.dt, e.m, e.vstage, e.wstage);
+    motion_vertex_lanes<DIM>(i - e.v_begin, int(tid & 3), true, e.nv, e.X, e.x, e.clock[0], e.dt, e.m, e.vstage,
+                             e.wstage);
 }
 
 // x_n <- x_{n+1} for every request (a no-op for finished ones, whose stage
